@@ -1,0 +1,267 @@
+/*
+ * gna_hip.h -- C ABI of libgna_hip.so, the MI355X (gfx950) library for the
+ * data-parallel hot path of the GNA reactor-antineutrino prediction chain:
+ *
+ *   P_ee(E; L, theta) -> sum over baselines -> x flux x IBD cross section
+ *   -> Gauss-Legendre bin integration -> Gaussian energy smearing
+ *   -> Poisson chi^2 and its gradient with respect to
+ *      theta = (dm2_21 [eV^2], dm2_31 [eV^2], sin^2 th12, sin^2 th13, norm).
+ *
+ * Paper: A. Fatkina et al., "CUDA Support in GNA Data Analysis Framework",
+ * arXiv:1804.07682.  Sec. 4.1 defines the oscillation probability; Sec. 2.1
+ * and 4.2 define the conventions kept here:
+ *   - a transformation maps read-only input vectors and scalar "variables"
+ *     to output vectors (Sec. 2.1, Fig. 2);
+ *   - data lives on the outputs, inputs are views (Sec. 2.1, Sec. 4.2);
+ *   - all memory is allocated at the configuration stage (Sec. 4.2): this
+ *     library never allocates device memory -- the caller hands it every
+ *     buffer, including a workspace sized by the *_workspace_size calls;
+ *   - the status of the GPU computation is available on the host afterwards
+ *     (Sec. 4.2): every call returns a status code, and device-side domain
+ *     errors are latched in the plan and read with gna_plan_status.
+ *
+ * Plain C: pointers, sizes, no C++ or torch types.  A "stream" argument is a
+ * hipStream_t passed as void* (NULL = the default stream).  "_dev" pointers
+ * are device memory on the current HIP device; "_host" pointers (and every
+ * pointer inside gna_problem / gna_model) are host memory, read during the
+ * call only.  Device buffers must be 16-byte aligned unless stated.
+ *
+ * Threading: calls on different plans are independent.  One plan must not be
+ * evaluated concurrently on two streams (its workspace holds per-eval
+ * counters).  The last error message is thread-local.
+ */
+#ifndef GNA_HIP_H
+#define GNA_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GNA_ABI_VERSION 1
+
+/* ---- status codes -------------------------------------------------------- */
+#define GNA_OK 0
+#define GNA_E_INVAL (-1)       /* bad argument, detected on the host before any launch   */
+#define GNA_E_DOMAIN (-2)      /* a device-side domain error was latched (see below)     */
+#define GNA_E_HIP (-3)         /* a HIP runtime call failed (message names it)           */
+#define GNA_E_WORKSPACE (-4)   /* workspace missing, misaligned or too small              */
+#define GNA_E_UNSUPPORTED (-5) /* valid request outside what this build implements        */
+
+/* ---- precision modes ----------------------------------------------------- */
+/* GNA_FP64: every step in FP64.
+ * GNA_MIXED: oscillation phases and their reduction modulo pi/2 in FP64 (a
+ *   52 km baseline puts phases at ~1e2-1e3 rad, where FP32 loses the phase);
+ *   sin^2 / cos^2 / sin 2phi of the reduced argument, the probability, the
+ *   flux products, the bin sums and the smearing in FP32 with FP32
+ *   accumulation; chi^2, d chi^2/d nu and the final gradient sums in FP64. */
+#define GNA_FP64 0
+#define GNA_MIXED 1
+
+int gna_abi_version(void);
+/* Static description of a status code; never NULL. */
+const char* gna_strerror(int status);
+/* Thread-local description of the last error raised on this thread ("" if none). */
+const char* gna_last_error_message(void);
+
+/* ---- elementwise survival probability (Sec. 4.1, alpha = beta = e) ------- */
+/*
+ * P_dev[i] = sum_r w_r * P_ee(E_dev[i]; L_r, theta),  i < n, where
+ *   P_ee = 1 - 4 sum_{i>j} |U_ei|^2 |U_ej|^2 sin^2(dm2_ij L / 4E)
+ * (the Sec. 4.1 formula with alpha = beta = e, whose Im term vanishes), with
+ * |U_e1|^2 = (1-s12)(1-s13), |U_e2|^2 = s12 (1-s13), |U_e3|^2 = s13,
+ * dm2_32 = dm2_31 - dm2_21, and the phase dm2 L/4E = K dm2[eV^2] L[km]/E[MeV],
+ * K = 1266.9326794198487 (hbar c = 197.3269804 MeV fm).  One launch covers
+ * all n energies (Sec. 4.1: each energy is independent).
+ *
+ * E_dev     device, n doubles, E > 0 [MeV] (E <= 0 gives NaN in that slot).
+ * n         >= 0; n = 0 is a no-op.
+ * n_L       number of baselines, 1..64.
+ * L_km_host host, n_L baselines >= 0 [km].
+ * wL_host   host, n_L weights, or NULL for 1/n_L each (Fig. 4: one OscProb
+ *           per baseline on a shared energy vector, summed).
+ * theta_host host, 4 doubles (dm2_21, dm2_31, s12, s13); s12, s13 in [0, 1].
+ * P_dev     device output, n doubles (GNA_FP64) or n floats (GNA_MIXED).
+ * prec      GNA_FP64 or GNA_MIXED.
+ * Asynchronous on `stream`.  Errors: GNA_E_INVAL (bad sizes, NULL, s out of
+ * [0,1], misaligned pointers), GNA_E_HIP (launch failure).
+ * Accuracy: phases are reduced exactly enough for |phase| < 1e9 rad.
+ */
+int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double* L_km_host,
+            const double* wL_host, const double* theta_host, void* P_dev, int32_t prec,
+            void* stream);
+
+/* ---- chain description --------------------------------------------------- */
+/*
+ * Model constants shared by all problems of a plan (readings of quantities the
+ * paper leaves to the experiment's model):
+ *   spectrum      S(E) = exp(spec[0] + spec[1] E + spec[2] E^2 + spec[3] E^3)
+ *   IBD section   sigma(E) = x sqrt(x^2 - m_e^2), x = E - xsec_delta, 0 if x <= m_e
+ *   flux factor   f_k = n0 * w_k * S(E_k) * sigma(E_k)   (w_k quadrature weight)
+ *   resolution    sigma_E = res_a sqrt(E) at the true-bin centre (res_a >= 0)
+ */
+typedef struct gna_model {
+  double spec[4];
+  double xsec_delta;
+  double m_e;
+  double n0;
+  double res_a;
+} gna_model;
+
+/*
+ * One prediction problem (a "geometry"):
+ *   n_bins    analysis bins, 1..4096, on strictly increasing edges[n_bins+1] > 0;
+ *   gl_order  Gauss-Legendre order 1..64, n_sub >= 1 equal sub-intervals per
+ *             bin; points per bin gl_order * n_sub <= 65536;
+ *   L_km[n_L], wL[n_L] (or NULL = 1/n_L): baselines and weights, n_L 1..64;
+ *   data      observed counts per bin (>= 0), used by chi^2.
+ * The chain for one parameter point theta:
+ *   Pbar_k = sum_r wL_r P_ee(E_k; L_r, theta)            (Sec. 4.1, Fig. 4)
+ *   mu_j   = norm * sum_{k in bin j} f_k Pbar_k           (bin integration)
+ *   nu_i   = sum_j R_ij mu_j,                             (smearing)
+ *     R_ij = (erf((e_{i+1}-Ebar_j)/(sqrt2 s_j)) - erf((e_i-Ebar_j)/(sqrt2 s_j)))/2,
+ *     Ebar_j = (e_j + e_{j+1})/2, s_j = res_a sqrt(Ebar_j)
+ *   chi2   = 2 sum_i [nu_i - d_i + d_i ln(d_i/nu_i)]      (Baker-Cousins Poisson)
+ * and its gradient d chi2 / d theta (5 values).  Quadrature points of bin j:
+ * sub-interval edges u_s = e_j + ((e_{j+1}-e_j) s)/n_sub, u_{n_sub} = e_{j+1};
+ * on [a,b]: E = (a+b)/2 + ((b-a)/2) t_i, w = ((b-a)/2) w_i.
+ */
+typedef struct gna_problem {
+  int32_t n_bins;
+  const double* edges;
+  int32_t gl_order;
+  int32_t n_sub;
+  int32_t n_L;
+  const double* L_km;
+  const double* wL;
+  const double* data;
+} gna_problem;
+
+/*
+ * Launch-shape options (all 0 = automatic).  Autotuned values come from
+ * gna_plan_autotune.
+ *   threads        work-group size: 64, 128, 256, 512 or 1024
+ *   lanes_per_bin  lanes cooperating on one bin: power of two, 1..64
+ *   chunks         pieces each bin's points are split into (their partial
+ *                  sums are added in a fixed order, so results do not depend
+ *                  on scheduling): 1..1024
+ *   persistent     0: one work-group per tile; 1: a grid of
+ *                  (CUs x occupancy) work-groups pulling tiles from a queue
+ *   smear_mfma     (chain plans only) 1: batched kernel with the smearing as
+ *                  a block-banded MFMA GEMM (needs n_bins <= 256);
+ *                  0: banded smearing on the vector units; -1: automatic
+ */
+typedef struct gna_launch_opts {
+  int32_t threads;
+  int32_t lanes_per_bin;
+  int32_t chunks;
+  int32_t persistent;
+  int32_t smear_mfma;
+} gna_launch_opts;
+
+typedef struct gna_plan gna_plan;
+
+/* ---- one geometry, a batch of parameter points (configuration stage) ---- */
+/*
+ * Sizes the workspace of a chain plan for up to max_batch parameter points.
+ * Host only (no HIP call).  opts may be NULL.  Errors: GNA_E_INVAL.
+ */
+int gna_chain_workspace_size(const gna_model* model, const gna_problem* problem,
+                             int32_t prec, int32_t max_batch, const gna_launch_opts* opts,
+                             size_t* bytes);
+/*
+ * Configuration stage (Sec. 2, two-stage model; Sec. 4.2, allocation at
+ * configuration): copies the description into ws_dev and builds, with
+ * device kernels, the Gauss-Legendre rule, the quadrature energies, the flux
+ * factors f_k and the banded smearing matrix.  ws_dev: device, 256-byte
+ * aligned, ws_bytes >= gna_chain_workspace_size; owned by the caller, must
+ * outlive the plan.  Synchronizes `stream` before returning.  *out receives a
+ * host-allocated plan, freed by gna_plan_destroy.
+ * Errors: GNA_E_INVAL, GNA_E_WORKSPACE, GNA_E_HIP, GNA_E_UNSUPPORTED.
+ */
+int gna_chain_create(const gna_model* model, const gna_problem* problem, int32_t prec,
+                     int32_t max_batch, const gna_launch_opts* opts, void* ws_dev,
+                     size_t ws_bytes, void* stream, gna_plan** out);
+/*
+ * Computational stage: chi^2 (and gradient) of B parameter points in one
+ * launch sequence, asynchronous on `stream`.
+ *   params_dev  device, [B][5] doubles (dm2_21, dm2_31, s12, s13, norm)
+ *   chi2_dev    device output, [B] doubles
+ *   grad_dev    device output, [B][5] doubles, or NULL (no gradient work)
+ *   pred_dev    device output, [B][n_bins] doubles (nu), or NULL (Fig. 6:
+ *               reading an intermediate output costs one extra write)
+ * 1 <= B <= max_batch.  Parameters are not range-checked on the host (they
+ * are device data): s12, s13 outside [0, 1] or nu_i <= 0 latch GNA_E_DOMAIN
+ * (read it with gna_plan_status) and give NaN for that point.
+ * Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_chain_eval(gna_plan* plan, const double* params_dev, int32_t B, double* chi2_dev,
+                   double* grad_dev, double* pred_dev, void* stream);
+
+/* ---- uneven batch: independent fits, one parameter point each ----------- */
+/*
+ * As the chain calls, for n_fits independent problems (each its own bins,
+ * order, baselines and data), evaluated together in one launch.  Tiles of all
+ * fits are queued largest-first.  pred_dev (optional) is the concatenation of
+ * the fits' nu vectors in fit order.
+ */
+int gna_fitset_workspace_size(const gna_model* model, const gna_problem* problems,
+                              int32_t n_fits, int32_t prec, const gna_launch_opts* opts,
+                              size_t* bytes);
+int gna_fitset_create(const gna_model* model, const gna_problem* problems, int32_t n_fits,
+                      int32_t prec, const gna_launch_opts* opts, void* ws_dev,
+                      size_t ws_bytes, void* stream, gna_plan** out);
+/* params_dev [n_fits][5]; chi2_dev [n_fits]; grad_dev [n_fits][5] or NULL;
+ * pred_dev [sum n_bins] or NULL. */
+int gna_fitset_eval(gna_plan* plan, const double* params_dev, double* chi2_dev,
+                    double* grad_dev, double* pred_dev, void* stream);
+
+/* ---- plan queries and lifecycle ------------------------------------------ */
+/*
+ * Synchronizes `stream`, then reads and clears the plan's device status word.
+ * *device_status (may be NULL) receives the raw word (bit 0: a mixing
+ * parameter outside [0, 1]; bit 1: some nu_i <= 0 or not finite).
+ * Returns GNA_E_DOMAIN if any bit was set, else GNA_OK (or GNA_E_HIP).
+ */
+int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
+/* Launch shape in use: writes 5 ints (threads, lanes_per_bin, chunks,
+ * persistent, smear_mfma) and the number of tiles of one evaluation. */
+int gna_plan_shape(const gna_plan* plan, int32_t shape_out[5], int64_t* n_tiles);
+/*
+ * Project-written autotuner: times each candidate launch shape of this plan
+ * on `stream` with HIP events (median of `reps` evaluations at params_dev,
+ * B points for chain plans), keeps the fastest, and, if cache_path is not
+ * NULL, records it in a small JSON file keyed by the plan's shape bucket,
+ * precision and GPU architecture (read back by gna_plan_autotune before
+ * timing: a hit costs no launch).  Writes chi2/grad scratch into the
+ * caller's chi2_dev / grad_dev.  Returns GNA_OK and the chosen shape.
+ */
+int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32_t B, double* chi2_dev,
+                      double* grad_dev, int32_t reps, const char* cache_path, void* stream,
+                      int32_t shape_out[5]);
+/* Frees the host-side plan (the caller still owns the workspace). */
+int gna_plan_destroy(gna_plan* plan);
+
+/* ---- unfused transformations (vector in / vector out) -------------------- */
+/*
+ * Gauss-Legendre rule of order 1..64 on [-1, 1] (nodes ascending, weights),
+ * computed on the device into t_dev[order], w_dev[order].  Synchronous.
+ */
+int gna_gl_nodes(int32_t order, double* t_dev, double* w_dev, void* stream);
+/*
+ * Configuration-stage tables of problem `index` of a plan (Fig. 6-style
+ * intermediate read): quadrature energies E_dev[n_bins*ppb], flux factors
+ * f_dev[n_bins*ppb] (as doubles), and the dense smearing matrix
+ * R_dev[n_bins][n_bins] (row = reconstructed bin), expanded from the band.
+ * Any output may be NULL.  Asynchronous.
+ */
+int gna_plan_tables(const gna_plan* plan, int32_t index, double* E_dev, double* f_dev,
+                    double* R_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GNA_HIP_H */

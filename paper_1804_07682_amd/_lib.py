@@ -1,0 +1,107 @@
+"""ctypes loader for ``libgna_hip.so`` (argument marshalling only).
+
+There is no fallback: if the library is missing or cannot be loaded, every
+entry point raises.  Build it with ``python -m paper_1804_07682_amd.build``
+(or ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libgna_hip.so")
+
+GNA_OK = 0
+GNA_E_INVAL = -1
+GNA_E_DOMAIN = -2
+GNA_E_HIP = -3
+GNA_E_WORKSPACE = -4
+GNA_E_UNSUPPORTED = -5
+GNA_FP64 = 0
+GNA_MIXED = 1
+
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+
+
+class GnaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class Model(C.Structure):
+    _fields_ = [("spec", C.c_double * 4), ("xsec_delta", C.c_double), ("m_e", C.c_double),
+                ("n0", C.c_double), ("res_a", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("edges", _dp), ("gl_order", C.c_int32),
+                ("n_sub", C.c_int32), ("n_L", C.c_int32), ("L_km", _dp), ("wL", _dp),
+                ("data", _dp)]
+
+
+class LaunchOpts(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("lanes_per_bin", C.c_int32), ("chunks", C.c_int32),
+                ("persistent", C.c_int32), ("smear_mfma", C.c_int32)]
+
+
+class Plan(C.Structure):
+    pass
+
+
+_PlanP = C.POINTER(Plan)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "gna_abi_version": (C.c_int, []),
+    "gna_strerror": (C.c_char_p, [C.c_int]),
+    "gna_last_error_message": (C.c_char_p, []),
+    "gna_pee": (C.c_int, [_vp, C.c_int64, C.c_int32, _dp, _dp, _dp, _vp, C.c_int32, _vp]),
+    "gna_chain_workspace_size": (C.c_int, [C.POINTER(Model), C.POINTER(Problem), C.c_int32,
+                                           C.c_int32, C.POINTER(LaunchOpts),
+                                           C.POINTER(C.c_size_t)]),
+    "gna_chain_create": (C.c_int, [C.POINTER(Model), C.POINTER(Problem), C.c_int32, C.c_int32,
+                                   C.POINTER(LaunchOpts), _vp, C.c_size_t, _vp,
+                                   C.POINTER(_PlanP)]),
+    "gna_chain_eval": (C.c_int, [_PlanP, _vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "gna_fitset_workspace_size": (C.c_int, [C.POINTER(Model), C.POINTER(Problem), C.c_int32,
+                                            C.c_int32, C.POINTER(LaunchOpts),
+                                            C.POINTER(C.c_size_t)]),
+    "gna_fitset_create": (C.c_int, [C.POINTER(Model), C.POINTER(Problem), C.c_int32, C.c_int32,
+                                    C.POINTER(LaunchOpts), _vp, C.c_size_t, _vp,
+                                    C.POINTER(_PlanP)]),
+    "gna_fitset_eval": (C.c_int, [_PlanP, _vp, _vp, _vp, _vp, _vp]),
+    "gna_plan_status": (C.c_int, [_PlanP, _vp, C.POINTER(C.c_int32)]),
+    "gna_plan_shape": (C.c_int, [_PlanP, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "gna_plan_autotune": (C.c_int, [_PlanP, _vp, C.c_int32, _vp, _vp, C.c_int32, C.c_char_p,
+                                    _vp, C.POINTER(C.c_int32)]),
+    "gna_plan_destroy": (C.c_int, [_PlanP]),
+    "gna_gl_nodes": (C.c_int, [C.c_int32, _vp, _vp, _vp]),
+    "gna_plan_tables": (C.c_int, [_PlanP, C.c_int32, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load the library (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is not built; run paper_1804_07682_amd/build.py")
+    lib = C.CDLL(LIBPATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != GNA_OK:
+        msg = load().gna_last_error_message().decode()
+        raise GnaError(status, f"{what}: {msg}" if what else msg)

@@ -1,0 +1,334 @@
+"""Python binding of libgna_hip.so with the same names as the C ABI.
+
+Argument marshalling only: torch supplies device memory (tensors, the plan
+workspace) and the current HIP stream; every step of the chain runs in the
+library's kernels.  Problems and models are plain dicts (see ``workloads``):
+
+* ``problem``: ``edges`` (n_bins+1), ``gl_order``, ``n_sub``, ``L`` (km),
+  ``wL`` (or None), ``data`` (n_bins counts);
+* ``model``: ``spec`` (4 exponent coefficients), ``xsec_delta``, ``m_e``,
+  ``n0``, ``res_a``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import GNA_FP64, GNA_MIXED, GnaError, LaunchOpts, Model, Problem, check, load
+
+PREC = {"fp64": GNA_FP64, "mixed": GNA_MIXED, GNA_FP64: GNA_FP64, GNA_MIXED: GNA_MIXED}
+
+
+def _prec(p) -> int:
+    if p not in PREC:
+        raise ValueError(f"precision must be 'fp64' or 'mixed', got {p!r}")
+    return PREC[p]
+
+
+def _stream(device=None) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def abi_version() -> int:
+    return int(load().gna_abi_version())
+
+
+def make_model(model: dict) -> Model:
+    m = Model()
+    for i, a in enumerate(model["spec"]):
+        m.spec[i] = float(a)
+    m.xsec_delta = float(model["xsec_delta"])
+    m.m_e = float(model["m_e"])
+    m.n0 = float(model["n0"])
+    m.res_a = float(model["res_a"])
+    return m
+
+
+def make_problem(problem: dict, keep: list) -> Problem:
+    edges = _f64(problem["edges"])
+    L = _f64(np.atleast_1d(problem["L"]))
+    wL = None if problem.get("wL") is None else _f64(problem["wL"])
+    nb = edges.size - 1
+    data = _f64(problem["data"]) if problem.get("data") is not None else np.zeros(nb)
+    keep.extend([edges, L, wL, data])
+    p = Problem()
+    p.n_bins = nb
+    p.edges = _dptr(edges)
+    p.gl_order = int(problem["gl_order"])
+    p.n_sub = int(problem.get("n_sub", 1))
+    p.n_L = L.size
+    p.L_km = _dptr(L)
+    p.wL = _dptr(wL)
+    p.data = _dptr(data)
+    return p
+
+
+def make_opts(opts) -> LaunchOpts | None:
+    if opts is None:
+        return None
+    o = LaunchOpts()
+    o.threads = int(opts.get("threads", 0))
+    o.lanes_per_bin = int(opts.get("lanes_per_bin", 0))
+    o.chunks = int(opts.get("chunks", 0))
+    o.persistent = int(opts.get("persistent", 0))
+    o.smear_mfma = int(opts.get("smear_mfma", -1))
+    return o
+
+
+def gna_pee(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Tensor | None = None):
+    """Baseline-weighted P_ee over a resident energy vector (Sec. 4.1).
+
+    E: CUDA float64 [n]; L, wL: baselines (km) and weights (host sequences);
+    theta: (dm2_21, dm2_31, s12, s13).  Returns float64 (fp64) or float32
+    (mixed) [n] on E's device, computed on the current stream.
+    """
+    _need_cuda(E, "E")
+    pr = _prec(prec)
+    L = _f64(np.atleast_1d(L))
+    wLa = None if wL is None else _f64(wL)
+    th = _f64(theta)[:4].copy()
+    odt = torch.float64 if pr == GNA_FP64 else torch.float32
+    if out is None:
+        out = torch.empty(E.numel(), dtype=odt, device=E.device)
+    else:
+        _need_cuda(out, "out", odt)
+        if out.numel() != E.numel():
+            raise ValueError("out has the wrong size")
+    check(load().gna_pee(_ptr(E), E.numel(), L.size, _dptr(L), _dptr(wLa), _dptr(th), _ptr(out),
+                         pr, _stream(E.device)), "gna_pee")
+    return out
+
+
+def gna_gl_nodes(order: int, device="cuda"):
+    t = torch.empty(order, dtype=torch.float64, device=device)
+    w = torch.empty(order, dtype=torch.float64, device=device)
+    check(load().gna_gl_nodes(order, _ptr(t), _ptr(w), _stream(t.device)), "gna_gl_nodes")
+    return t, w
+
+
+class _PlanBase:
+    kind = "chain"
+
+    def __init__(self):
+        self._plan = None
+        self.workspace = None
+
+    def _alloc(self, nbytes: int, device):
+        # torch's caching allocator returns >= 512-byte aligned blocks; over-
+        # allocate and round up so the workspace start is 256-byte aligned anyway.
+        raw = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.workspace = raw[off:off + int(nbytes)]
+        return self.workspace
+
+    def status(self):
+        """Synchronize, read and clear the device status word.  Raises GnaError on
+        a latched domain error; returns the raw word otherwise (0)."""
+        word = C.c_int32(0)
+        st = load().gna_plan_status(self._plan, _stream(self.device), C.byref(word))
+        if st == _lib.GNA_E_DOMAIN:
+            raise GnaError(st, load().gna_last_error_message().decode())
+        check(st, "gna_plan_status")
+        return word.value
+
+    def shape(self):
+        s = (C.c_int32 * 5)()
+        n = C.c_int64(0)
+        check(load().gna_plan_shape(self._plan, s, C.byref(n)), "gna_plan_shape")
+        keys = ("threads", "lanes_per_bin", "chunks", "persistent", "smear_mfma")
+        d = dict(zip(keys, list(s)))
+        d["n_tiles"] = n.value
+        return d
+
+    def tables(self, index=0, E=True, f=True, R=True):
+        """Configuration-stage tables of problem `index` (quadrature energies,
+        flux factors and the dense smearing matrix) as float64 tensors."""
+        pb = self.problems[index]
+        nb = len(pb["edges"]) - 1
+        n = nb * int(pb["gl_order"]) * int(pb.get("n_sub", 1))
+        dev = self.device
+        tE = torch.empty(n, dtype=torch.float64, device=dev) if E else None
+        tf = torch.empty(n, dtype=torch.float64, device=dev) if f else None
+        tR = torch.empty((nb, nb), dtype=torch.float64, device=dev) if R else None
+        check(load().gna_plan_tables(self._plan, index, _ptr(tE), _ptr(tf), _ptr(tR),
+                                     _stream(dev)), "gna_plan_tables")
+        return tE, tf, tR
+
+    def autotune(self, params: torch.Tensor, reps=10, cache_path=None):
+        _need_cuda(params, "params")
+        B = params.shape[0]
+        chi2 = torch.empty(B, dtype=torch.float64, device=self.device)
+        grad = torch.empty((B, 5), dtype=torch.float64, device=self.device)
+        s = (C.c_int32 * 5)()
+        path = None if cache_path is None else str(cache_path).encode()
+        check(load().gna_plan_autotune(self._plan, _ptr(params), B, _ptr(chi2), _ptr(grad), reps,
+                                       path, _stream(self.device), s), "gna_plan_autotune")
+        return self.shape()
+
+    def close(self):
+        if self._plan is not None:
+            load().gna_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Chain(_PlanBase):
+    """One geometry, a batch of up to ``max_batch`` parameter points
+    (``gna_chain_create`` / ``gna_chain_eval``)."""
+
+    kind = "chain"
+
+    def __init__(self, problem: dict, model: dict, max_batch: int = 1, prec="fp64", opts=None,
+                 device="cuda"):
+        super().__init__()
+        self.device = torch.device(device)
+        self.prec = _prec(prec)
+        self.max_batch = int(max_batch)
+        self.problems = [problem]
+        self.n_bins = len(problem["edges"]) - 1
+        keep = []
+        m = make_model(model)
+        p = make_problem(problem, keep)
+        o = make_opts(opts)
+        nbytes = C.c_size_t(0)
+        lib = load()
+        check(lib.gna_chain_workspace_size(C.byref(m), C.byref(p), self.prec, self.max_batch,
+                                           C.byref(o) if o else None, C.byref(nbytes)),
+              "gna_chain_workspace_size")
+        ws = self._alloc(nbytes.value, self.device)
+        plan = _lib._PlanP()
+        check(lib.gna_chain_create(C.byref(m), C.byref(p), self.prec, self.max_batch,
+                                   C.byref(o) if o else None, _ptr(ws), nbytes.value,
+                                   _stream(self.device), C.byref(plan)), "gna_chain_create")
+        self._plan = plan
+
+    def eval(self, params: torch.Tensor, grad=True, pred=False, out=None):
+        """chi^2 [B] (and grad [B, 5], pred [B, n_bins]) for params [B, 5]."""
+        _need_cuda(params, "params")
+        if params.dim() == 1:
+            params = params.reshape(1, 5)
+        B = params.shape[0]
+        if params.shape[1] != 5:
+            raise ValueError("params must be [B, 5]")
+        dev = self.device
+        res = out if out is not None else {}
+        chi2 = res.get("chi2")
+        if chi2 is None:
+            chi2 = torch.empty(B, dtype=torch.float64, device=dev)
+        g = res.get("grad") if grad else None
+        if grad and g is None:
+            g = torch.empty((B, 5), dtype=torch.float64, device=dev)
+        pr = res.get("pred") if pred else None
+        if pred and pr is None:
+            pr = torch.empty((B, self.n_bins), dtype=torch.float64, device=dev)
+        check(load().gna_chain_eval(self._plan, _ptr(params), B, _ptr(chi2), _ptr(g), _ptr(pr),
+                                    _stream(dev)), "gna_chain_eval")
+        res = {"chi2": chi2}
+        if grad:
+            res["grad"] = g
+        if pred:
+            res["pred"] = pr
+        return res
+
+
+class FitSet(_PlanBase):
+    """Independent fits, one parameter point each, in one launch
+    (``gna_fitset_create`` / ``gna_fitset_eval``)."""
+
+    kind = "fitset"
+
+    def __init__(self, problems, model: dict, prec="fp64", opts=None, device="cuda"):
+        super().__init__()
+        self.device = torch.device(device)
+        self.prec = _prec(prec)
+        self.problems = list(problems)
+        F = len(self.problems)
+        self.n_fits = F
+        self.n_bins = [len(p["edges"]) - 1 for p in self.problems]
+        keep = []
+        arr = (Problem * F)()
+        for i, pb in enumerate(self.problems):
+            arr[i] = make_problem(pb, keep)
+        m = make_model(model)
+        o = make_opts(opts)
+        nbytes = C.c_size_t(0)
+        lib = load()
+        check(lib.gna_fitset_workspace_size(C.byref(m), arr, F, self.prec,
+                                            C.byref(o) if o else None, C.byref(nbytes)),
+              "gna_fitset_workspace_size")
+        ws = self._alloc(nbytes.value, self.device)
+        plan = _lib._PlanP()
+        check(lib.gna_fitset_create(C.byref(m), arr, F, self.prec, C.byref(o) if o else None,
+                                    _ptr(ws), nbytes.value, _stream(self.device), C.byref(plan)),
+              "gna_fitset_create")
+        self._plan = plan
+
+    def eval(self, params: torch.Tensor, grad=True, pred=False):
+        _need_cuda(params, "params")
+        if tuple(params.shape) != (self.n_fits, 5):
+            raise ValueError(f"params must be [{self.n_fits}, 5]")
+        dev = self.device
+        chi2 = torch.empty(self.n_fits, dtype=torch.float64, device=dev)
+        g = torch.empty((self.n_fits, 5), dtype=torch.float64, device=dev) if grad else None
+        pr = torch.empty(sum(self.n_bins), dtype=torch.float64, device=dev) if pred else None
+        check(load().gna_fitset_eval(self._plan, _ptr(params), _ptr(chi2), _ptr(g), _ptr(pr),
+                                     _stream(dev)), "gna_fitset_eval")
+        res = {"chi2": chi2}
+        if grad:
+            res["grad"] = g
+        if pred:
+            res["pred"] = pr
+        return res
+
+
+class Chi2Fn(torch.autograd.Function):
+    """chi^2 of a chain plan as a differentiable function of params [B, 5].
+
+    forward runs ``gna_chain_eval`` with the adjoint gradient and saves it;
+    backward returns grad_output[:, None] * grad (no second evaluation).
+    """
+
+    @staticmethod
+    def forward(ctx, params, plan):
+        res = plan.eval(params.detach().contiguous(), grad=True)
+        ctx.save_for_backward(res["grad"])
+        return res["chi2"]
+
+    @staticmethod
+    def backward(ctx, g_chi2):
+        (grad,) = ctx.saved_tensors
+        return g_chi2.reshape(-1, 1) * grad, None
+
+
+def chi2(params: torch.Tensor, plan: Chain) -> torch.Tensor:
+    return Chi2Fn.apply(params, plan)

@@ -1,0 +1,389 @@
+// The fused prediction chain on the GPU: one kernel evaluates, for a set of
+// parameter points, every step from the oscillation probability to chi^2 and
+// its gradient.
+//
+// Work decomposition.  A tile is (parameter point, block of bins, chunk of
+// each bin's quadrature points).  Inside a tile, G lanes share a bin: each
+// lane walks the bin's points (all baselines, Fig. 4) and accumulates
+//   mu0_j = sum_k f_k Pbar_k   and   J0_jc = sum_k f_k d Pbar_k / d theta_c,
+// then the G lanes are summed with cross-lane shuffles.  When a point's bins
+// fit one tile the results stay in LDS; otherwise each tile writes its
+// partial sums to the scratch region and the last tile of the point (agent-
+// scope counter, release/acquire fences) adds the chunks in a fixed order and
+// runs the tail.  Results are therefore independent of scheduling.
+//
+// Tail (one work-group per point):
+//   nu_i    = sum_j R_ij mu_j          banded R, one wavefront per 64-row slice
+//   chi2    = 2 sum_i [nu_i - d_i + d_i ln(d_i / nu_i)]     (FP64)
+//   gnu_i   = 2 (1 - d_i / nu_i)                            (FP64, stored in R)
+//   gmu_j   = sum_i R_ij gnu_i         the same band, walked by columns
+//   grad_c  = norm sum_j gmu_j J0_jc,  grad_norm = sum_j gmu_j mu0_j   (FP64 sums)
+#include <cmath>
+
+#include "gna_internal.h"
+#include "gna_math.h"
+
+namespace gna {
+namespace {
+
+template <class R>
+__device__ __forceinline__ R rfma(R a, R b, R c);
+template <>
+__device__ __forceinline__ double rfma<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float rfma<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+struct TileLds {
+  unsigned char* base;
+  int threads;
+  int max_bins;
+  template <class R>
+  __device__ R* stage() const {
+    return reinterpret_cast<R*>(base);
+  }
+  template <class R>
+  __device__ R* mu() const {
+    return reinterpret_cast<R*>(base + align16(threads * 5 * sizeof(R)));
+  }
+  template <class R>
+  __device__ R* gnu() const {
+    return reinterpret_cast<R*>(base + align16(threads * 5 * sizeof(R)) +
+                                align16(max_bins * sizeof(R)));
+  }
+  template <class R>
+  __device__ double* red() const {
+    return reinterpret_cast<double*>(base + align16(threads * 5 * sizeof(R)) +
+                                     2 * align16(max_bins * sizeof(R)));
+  }
+  template <class R>
+  __device__ int* flag() const {
+    return reinterpret_cast<int*>(red<R>() + (threads / kWave) * 6);
+  }
+  __device__ static size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+};
+
+template <class R, bool GRAD>
+__device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L) {
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  TileDev td;
+  if (a.tiles) {
+    td = a.tiles[t];
+  } else {
+    const ProbDev& p0 = a.probs[0];
+    td.point = (int32_t)(t / a.tiles_per_point);
+    const int local = (int)(t - (int64_t)td.point * a.tiles_per_point);
+    td.prob = 0;
+    td.bb = local / p0.C;
+    td.chunk = local - td.bb * p0.C;
+  }
+  const ProbDev pd = a.probs[td.prob];
+  const double* th = a.params + 5 * (int64_t)td.point;
+  const PeeCoef<R> k = pee_coef<R>(th);
+
+  // ---- point pass --------------------------------------------------------
+  const int G = pd.G;
+  const int lb = tid / G, g = tid - (tid / G) * G;
+  const int j = td.bb * pd.bins_per_tile + lb;
+  const int k0 = (int)((int64_t)td.chunk * pd.ppb / pd.C);
+  const int k1 = (int)((int64_t)(td.chunk + 1) * pd.ppb / pd.C);
+  R mu = R(0);
+  R J[4] = {R(0), R(0), R(0), R(0)};
+  if (lb < pd.bins_per_tile && j < pd.n_bins) {
+    const int64_t base = pd.pt_off + (int64_t)j * pd.ppb;
+    for (int kk = k0 + g; kk < k1; kk += G) {
+      const double E = a.E[base + kk];
+      const R fk = a.f[base + kk];
+      R pb = R(0);
+      R dpb[4] = {R(0), R(0), R(0), R(0)};
+      for (int r = 0; r < pd.n_L; ++r) {
+        const double q = (kPhase * a.L[pd.L_off + r]) / E;
+        const R wr = (R)a.wL[pd.L_off + r];
+        R P, dP[4];
+        pee_point<R, GRAD>(k, q, P, dP);
+        pb = rfma<R>(wr, P, pb);
+        if (GRAD) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) dpb[c] = rfma<R>(wr, dP[c], dpb[c]);
+        }
+      }
+      mu = rfma<R>(fk, pb, mu);
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) J[c] = rfma<R>(fk, dpb[c], J[c]);
+      }
+    }
+  }
+  // Sum the G lanes of each bin (groups are aligned inside a wavefront).
+  for (int off = G >> 1; off > 0; off >>= 1) {
+    mu += __shfl_xor(mu, off, kWave);
+    if (GRAD) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) J[c] += __shfl_xor(J[c], off, kWave);
+    }
+  }
+
+  const int nb = pd.n_bins;
+  const int tiles_of_point = pd.n_bin_blocks * pd.C;
+  const bool single = (tiles_of_point == 1);
+  R* stage = L.stage<R>();
+  R* sc = a.scratch + (a.tiles ? pd.scratch_off : (int64_t)td.point * a.scratch_stride);
+  if (g == 0 && lb < pd.bins_per_tile && j < nb) {
+    if (single) {
+      stage[lb * 5] = mu;
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) stage[lb * 5 + 1 + c] = J[c];
+      }
+    } else {
+      sc[(int64_t)(td.chunk * 5) * nb + j] = mu;
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sc[(int64_t)(td.chunk * 5 + 1 + c) * nb + j] = J[c];
+      }
+    }
+  }
+  int* flag = L.flag<R>();
+  if (!single) {
+    __threadfence();  // release this tile's partial sums at agent scope
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t prev = __hip_atomic_fetch_add(&a.counters[td.point], 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      *flag = (prev + 1 == (uint32_t)tiles_of_point) ? 1 : 0;
+    }
+    __syncthreads();
+    if (*flag == 0) return;  // not the last tile of this point
+    __threadfence();         // acquire the other tiles' partial sums
+    if (tid == 0) a.counters[td.point] = 0u;  // ready for the next evaluation
+  } else {
+    __syncthreads();
+  }
+
+  // ---- tail ----------------------------------------------------------------
+  const int C = pd.C;
+  auto mu0_of = [&](int jj) -> R {
+    if (single) return stage[jj * 5];
+    R s = R(0);
+    for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5) * nb + jj];
+    return s;
+  };
+  auto J0_of = [&](int jj, int cidx) -> R {
+    if (single) return stage[jj * 5 + 1 + cidx];
+    R s = R(0);
+    for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5 + 1 + cidx) * nb + jj];
+    return s;
+  };
+  const double norm = th[4];
+  const R normr = (R)norm;
+  R* mus = L.mu<R>();
+  R* gnus = L.gnu<R>();
+  for (int jj = tid; jj < nb; jj += NT) mus[jj] = normr * mu0_of(jj);
+  __syncthreads();
+
+  const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
+  const int nwaves = NT / kWave;
+  const SliceDev* slices = a.slices + pd.slice_off;
+  const double* dat = a.data + pd.bin_off;
+  double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)td.point * nb)
+                        : nullptr;
+  double chi = 0.0;
+  bool badnu = false;
+  for (int s = wave; s < pd.n_slices; s += nwaves) {
+    const SliceDev sd = slices[s];
+    const int i = s * kSlice + lane;
+    const R* rv = a.Rv + sd.off + lane;
+    R acc = R(0);
+    for (int dd = 0; dd < sd.nd; ++dd) {
+      const int jj = i + sd.dlo + dd;
+      const R m = ((unsigned)jj < (unsigned)nb) ? mus[jj] : R(0);
+      acc = rfma<R>(rv[(int64_t)dd * kSlice], m, acc);
+    }
+    if (i < nb) {
+      const double nu = (double)acc;
+      const double d = dat[i];
+      if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
+      double term = nu - d;
+      if (d > 0.0) term += d * log(d / nu);
+      chi += term;
+      gnus[i] = (R)(2.0 * (1.0 - d / nu));
+      if (pred) pred[i] = nu;
+    }
+  }
+  if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  double* red = L.red<R>();
+  chi = wave_sum(chi);
+  if (lane == 0) red[wave * 6] = chi;
+  __syncthreads();
+
+  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (GRAD) {
+    const int ncb = (nb + kSlice - 1) / kSlice;
+    for (int cb = wave; cb < ncb; cb += nwaves) {
+      const int jc = cb * kSlice + lane;
+      R acc = R(0);
+      for (int s = 0; s < pd.n_slices; ++s) {
+        const SliceDev sd = slices[s];
+        const int col_lo = s * kSlice + sd.dlo;
+        const int col_hi = s * kSlice + (kSlice - 1) + sd.dlo + sd.nd - 1;
+        if (col_hi < cb * kSlice || col_lo > cb * kSlice + kSlice - 1) continue;
+        const int dbeg = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
+        const int dend = min(sd.dlo + sd.nd, kSlice * (cb - s) + kSlice);
+        for (int d = dbeg; d < dend; ++d) {
+          const int li = jc - d - s * kSlice;  // row inside slice s
+          if ((unsigned)li < (unsigned)kSlice) {
+            const int i = s * kSlice + li;
+            if (i < nb) acc = rfma<R>(a.Rv[sd.off + (int64_t)(d - sd.dlo) * kSlice + li], gnus[i], acc);
+          }
+        }
+      }
+      if (jc < nb) {
+        const double gmu = (double)acc;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gs[c] += gmu * (double)J0_of(jc, c);
+        gs[4] += gmu * (double)mu0_of(jc);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) red[wave * 6 + 1 + c] = gs[c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < nwaves; ++w) {
+      chisum += red[w * 6];
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g5[c] += red[w * 6 + 1 + c];
+      }
+    }
+    const bool bad = k.bad;
+    if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    a.chi2[td.point] = bad ? NAN : 2.0 * chisum;
+    if (GRAD && a.grad) {
+      double* gp = a.grad + 5 * (int64_t)td.point;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * g5[c];
+      gp[4] = bad ? NAN : g5[4];
+    }
+  }
+}
+
+template <class R, bool GRAD, bool PERSIST>
+__global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  TileLds L{lds_raw, (int)blockDim.x, max_bins};
+  if (!PERSIST) {
+    process_tile<R, GRAD>(a, (int64_t)blockIdx.x, L);
+    return;
+  }
+  __shared__ uint32_t next;
+  for (;;) {
+    if (threadIdx.x == 0)
+      next = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t t = next;
+    __syncthreads();
+    if (t >= a.n_tiles) break;
+    process_tile<R, GRAD>(a, t, L);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // Every group increments the exit count once, after its last queue
+    // fetch; the last one resets the queue for the next launch.
+    const uint32_t done = __hip_atomic_fetch_add(&a.queue[1], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done + 1 == gridDim.x) {
+      a.queue[0] = 0u;
+      a.queue[1] = 0u;
+    }
+  }
+}
+
+template <class R, bool GRAD, bool PERSIST>
+int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
+  const Shape& sh = p->shape;
+  const size_t lds = chain_lds_bytes(p, sh);
+  auto kern = chain_kernel<R, GRAD, PERSIST>;
+  int64_t grid = a.n_tiles;
+  if (PERSIST) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, sh.threads, lds) != hipSuccess ||
+        occ < 1)
+      occ = 1;
+    grid = std::min<int64_t>(a.n_tiles, (int64_t)occ * p->cu_count);
+  }
+  if (grid < 1) return GNA_OK;
+  if (grid > 0x7fffffffLL / sh.threads)
+    return fail(GNA_E_UNSUPPORTED, "%lld tiles exceed one launch; use the persistent shape",
+                (long long)grid);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lds, s, a, p->max_bins);
+  return check_hip(hipGetLastError(), "chain_kernel launch");
+}
+
+template <class R>
+int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
+             double* pred, hipStream_t s) {
+  unsigned char* w = p->ws;
+  const Layout& L = p->lay;
+  ChainArgs<R> a{};
+  a.probs = (const ProbDev*)(w + L.probs);
+  if (p->kind == kChain) {
+    a.tiles = nullptr;
+    a.tiles_per_point = (int32_t)p->n_tiles;
+    a.n_tiles = (int64_t)B * p->n_tiles;
+    a.scratch_stride = (int64_t)p->ccap * 5 * p->probs[0].n_bins;
+  } else {
+    a.tiles = (const TileDev*)(w + L.tiles);
+    a.tiles_per_point = 0;
+    a.n_tiles = p->n_tiles;
+    a.scratch_stride = 0;
+  }
+  a.want_grad = grad ? 1 : 0;
+  a.E = (const double*)(w + L.E);
+  a.f = (const R*)(w + L.f);
+  a.L = (const double*)(w + L.L);
+  a.wL = (const double*)(w + L.wL);
+  a.data = (const double*)(w + L.data);
+  a.slices = (const SliceDev*)(w + L.slices);
+  a.Rv = (const R*)(w + L.Rv);
+  a.params = params;
+  a.scratch = (R*)(w + L.scratch);
+  a.counters = (uint32_t*)(w + L.counters);
+  a.status = (uint32_t*)(w + L.status);
+  a.queue = (uint32_t*)(w + L.queue);
+  a.chi2 = chi2;
+  a.grad = grad;
+  a.pred = pred;
+  const bool pers = p->shape.persistent != 0;
+  if (grad) {
+    return pers ? launch_t<R, true, true>(p, a, s) : launch_t<R, true, false>(p, a, s);
+  }
+  return pers ? launch_t<R, false, true>(p, a, s) : launch_t<R, false, false>(p, a, s);
+}
+
+}  // namespace
+
+int launch_chain(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
+                 double* pred, hipStream_t s) {
+  if (p->prec == GNA_FP64) return launch_r<double>(p, params, B, chi2, grad, pred, s);
+  return launch_r<float>(p, params, B, chi2, grad, pred, s);
+}
+
+}  // namespace gna

@@ -1,0 +1,153 @@
+// Internal declarations of libgna_hip.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gna_hip.h"
+
+namespace gna {
+
+// ---- limits ----------------------------------------------------------------
+constexpr int kMaxBins = 4096;      // LDS holds mu and d chi2/d nu of one problem
+constexpr int kMaxOrder = 64;       // Gauss-Legendre order
+constexpr int kMaxPPB = 65536;      // points per bin
+constexpr int kMaxBaselines = 64;
+constexpr int kSlice = 64;          // rows per smearing-band slice (one wavefront)
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kGLTable = kMaxOrder * (kMaxOrder + 1) / 2;  // rules of order 1..64
+constexpr double kBandZ = 6.0;      // erf(z) == +-1 in FP64 beyond |z| = 5.93
+
+// ---- device-side descriptors (live in the workspace) -----------------------
+struct ProbDev {
+  int32_t n_bins;
+  int32_t ppb;            // quadrature points per bin = order * n_sub
+  int32_t n_L;
+  int32_t order;
+  int32_t n_sub;
+  int32_t G;              // lanes per bin
+  int32_t C;              // chunks per bin
+  int32_t bins_per_tile;  // threads / G
+  int32_t n_bin_blocks;
+  int32_t n_slices;
+  int64_t pt_off;         // first quadrature point (E, f arrays)
+  int64_t bin_off;        // first bin in data / pred (fitset) arrays
+  int64_t edge_off;       // first edge
+  int64_t L_off;          // first baseline
+  int64_t slice_off;      // first band slice
+  int64_t scratch_off;    // fitset: first scratch element of this fit
+};
+
+// One 64-row slice of the banded smearing matrix: rows i = 64 s + l, l < 64,
+// diagonals d = dlo .. dlo + nd - 1 hold R[i][i + d] at off + (d - dlo) * 64 + l.
+struct SliceDev {
+  int32_t dlo;
+  int32_t nd;
+  int64_t off;
+};
+
+struct TileDev {
+  int32_t point;  // parameter point (fitset: fit index)
+  int32_t prob;   // problem index
+  int32_t bb;     // bin block
+  int32_t chunk;  // chunk of each bin's points
+};
+
+// Arguments of the generic tile kernel (by value).
+template <class R>
+struct ChainArgs {
+  const ProbDev* probs;
+  const TileDev* tiles;      // NULL: chain plan, tiles decoded from the index
+  int64_t n_tiles;
+  int32_t tiles_per_point;   // chain plan only
+  int32_t want_grad;
+  int64_t scratch_stride;    // chain plan: scratch elements per parameter point
+  const double* E;
+  const R* f;
+  const double* L;
+  const double* wL;
+  const double* data;
+  const SliceDev* slices;
+  const R* Rv;
+  const double* params;
+  R* scratch;
+  uint32_t* counters;
+  uint32_t* status;
+  uint32_t* queue;
+  double* chi2;
+  double* grad;
+  double* pred;
+};
+
+enum StatusBits : uint32_t { kBadMixing = 1u, kBadPrediction = 2u };
+
+// ---- host-side plan ---------------------------------------------------------
+enum PlanKind { kChain = 0, kFitset = 1 };
+
+struct Layout {
+  size_t probs = 0, slices = 0, slice_prob = 0, tiles = 0, E = 0, f = 0, L = 0, wL = 0,
+         edges = 0, data = 0, gl = 0, Rv = 0, scratch = 0, counters = 0, queue = 0, status = 0,
+         Rdense = 0, total = 0;
+};
+
+struct Shape {
+  int threads = 256, G = 1, C = 1, persistent = 0, mfma = 0;
+};
+
+}  // namespace gna
+
+struct gna_plan {
+  int kind;
+  int prec;
+  int n_probs;
+  int n_points;           // chain: max_batch; fitset: n_fits
+  int64_t total_pts;
+  int64_t total_bins;
+  int64_t total_slices;
+  int64_t total_band;     // stored band entries
+  int max_bins;
+  int ccap;               // largest chunk count the scratch is sized for
+  int64_t tile_capacity;  // fitset: tile-list capacity
+  int64_t scratch_elems;
+  gna::Shape shape;
+  int64_t n_tiles;        // fitset: tiles in the queue; chain: tiles per point
+  int cu_count;
+  size_t lds_limit;
+  char arch[64];
+  unsigned char* ws;
+  size_t ws_bytes;
+  gna::Layout lay;
+  gna_model model;
+  std::vector<gna::ProbDev> probs;     // host copy of the device descriptors
+  std::vector<gna::SliceDev> slices;   // host copy
+  std::vector<double> edges_host;      // concatenated edges
+};
+
+namespace gna {
+
+// ---- error plumbing ----------------------------------------------------------
+int fail(int code, const char* fmt, ...);
+int check_hip(hipError_t e, const char* what);
+void clear_error();
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Launch helpers implemented in the .hip files.
+int launch_chain(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
+                 double* pred, hipStream_t s);
+int launch_scan(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
+                double* pred, hipStream_t s);
+int build_scan_tables(gna_plan* p, hipStream_t s);
+bool scan_supported(const gna_plan* p);
+size_t scan_dense_bytes(const gna_plan* p);
+size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
+// Sets the per-problem tiling of `sh` (and, for a fitset, rebuilds and
+// uploads the tile list when the plan has a workspace).
+int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s);
+std::vector<Shape> shape_candidates(const gna_plan* p);
+
+}  // namespace gna

@@ -1,0 +1,188 @@
+// Device math of the oscillation step: phase, reduction modulo pi/2 and the
+// trigonometric terms of the survival probability (Sec. 4.1).
+//
+// The library is compiled with -ffp-contract=off: every fused multiply-add
+// below is written out, every other operation is a single IEEE rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "trig_coeffs.h"
+
+namespace gna {
+
+// Phase constant: the Sec. 4.1 phase dm2_ij L / (4 E) (natural units) equals
+// K * dm2[eV^2] * L[km] / E[MeV] with K = 1e-3 / (4 hbar c[eV m]),
+// hbar c = 197.3269804 MeV fm; K is the double 1266.9326794198487.
+constexpr double kPhase = 1266.9326794198487;
+
+__device__ __forceinline__ double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// phi = m * pi/2 + r with |r| <= pi/4 (+ rounding), m = rint(phi * 2/pi).
+// Three-part Cody-Waite subtraction with FMAs: each step is one rounding of
+// an exactly formed product, so r carries ~1 ulp absolute error for
+// |m| < 2^52; `odd` is the parity of m (computed in FP64, no integer overflow).
+__device__ __forceinline__ double reduce_pio2(double phi, bool& odd) {
+  const double m = __builtin_rint(phi * GNA_TWO_OVER_PI);
+  double r = dfma(-m, GNA_PIO2_1, phi);
+  r = dfma(-m, GNA_PIO2_2, r);
+  r = dfma(-m, GNA_PIO2_3, r);
+  const double h = m * 0.5;
+  odd = (h != __builtin_rint(h));
+  return r;
+}
+
+// sin r, cos r on |r| <= pi/4 (minimax kernels from trig_coeffs.h).
+__device__ __forceinline__ void sincos_kernel(double r, double& s, double& c) {
+  const double x = r * r;
+  double ps = GNA_SD5;
+  ps = dfma(ps, x, GNA_SD4);
+  ps = dfma(ps, x, GNA_SD3);
+  ps = dfma(ps, x, GNA_SD2);
+  ps = dfma(ps, x, GNA_SD1);
+  ps = dfma(ps, x, GNA_SD0);
+  s = dfma(r * x, ps, r);
+  double pc = GNA_CD5;
+  pc = dfma(pc, x, GNA_CD4);
+  pc = dfma(pc, x, GNA_CD3);
+  pc = dfma(pc, x, GNA_CD2);
+  pc = dfma(pc, x, GNA_CD1);
+  pc = dfma(pc, x, GNA_CD0);
+  c = dfma(x * x, pc, dfma(-0.5, x, 1.0));
+}
+
+__device__ __forceinline__ void sincos_kernel(float r, float& s, float& c) {
+  const float x = r * r;
+  float ps = GNA_SF2;
+  ps = ffma(ps, x, GNA_SF1);
+  ps = ffma(ps, x, GNA_SF0);
+  s = ffma(r * x, ps, r);
+  float pc = GNA_CF2;
+  pc = ffma(pc, x, GNA_CF1);
+  pc = ffma(pc, x, GNA_CF0);
+  c = ffma(x * x, pc, ffma(-0.5f, x, 1.0f));
+}
+
+// sin^2 r on |r| <= pi/4.
+__device__ __forceinline__ double sin2_kernel(double r) {
+  const double x = r * r;
+  double p = GNA_QD7;
+  p = dfma(p, x, GNA_QD6);
+  p = dfma(p, x, GNA_QD5);
+  p = dfma(p, x, GNA_QD4);
+  p = dfma(p, x, GNA_QD3);
+  p = dfma(p, x, GNA_QD2);
+  p = dfma(p, x, GNA_QD1);
+  p = dfma(p, x, GNA_QD0);
+  return dfma(x * x, p, x);
+}
+
+__device__ __forceinline__ float sin2_kernel(float r) {
+  const float x = r * r;
+  float p = GNA_QF3;
+  p = ffma(p, x, GNA_QF2);
+  p = ffma(p, x, GNA_QF1);
+  p = ffma(p, x, GNA_QF0);
+  return ffma(x * x, p, x);
+}
+
+template <class R>
+__device__ __forceinline__ R to_r(double x) { return static_cast<R>(x); }
+
+// cos^2(phi) only (probability without tangents).  The reduction is FP64;
+// the kernel runs in R (double, or float for the mixed-precision mode).
+template <class R>
+__device__ __forceinline__ R cos2_phase(double phi) {
+  bool odd;
+  const double r = reduce_pio2(phi, odd);
+  const R s2 = sin2_kernel(to_r<R>(r));
+  const R c2 = R(1) - s2;  // >= 1/2: no cancellation
+  return odd ? s2 : c2;
+}
+
+// sin^2(phi), cos^2(phi) and sin(2 phi) of one phase.
+template <class R>
+struct PhaseTerms {
+  R S, C, T;
+};
+
+template <class R>
+__device__ __forceinline__ PhaseTerms<R> phase_terms(double phi) {
+  bool odd;
+  const double r = reduce_pio2(phi, odd);
+  R s, c;
+  sincos_kernel(to_r<R>(r), s, c);
+  const R s2 = s * s, c2 = c * c;
+  const R sc = s * c;
+  PhaseTerms<R> out;
+  out.S = odd ? c2 : s2;                 // sin^2(m pi/2 + r)
+  out.C = odd ? s2 : c2;                 // cos^2(m pi/2 + r)
+  out.T = odd ? R(-2) * sc : R(2) * sc;  // sin(m pi + 2 r) = (-1)^m sin 2r
+  return out;
+}
+
+// Per-parameter-point coefficients of P_ee written in the all-positive form
+//   P = K0 + A cos^2 phi21 + B1 cos^2 phi31 + B2 cos^2 phi32,
+//   A = 4 s12 (1-s12) (1-s13)^2, B = 4 s13 (1-s13), B1 = B (1-s12), B2 = B s12,
+//   K0 = 1 - A - B,
+// which equals the Sec. 4.1 expression 1 - A sin^2 phi21 - B1 sin^2 phi31 -
+// B2 sin^2 phi32 (cos^2 = 1 - sin^2) and keeps every term non-negative.
+// Derivatives (sin 2phi = d sin^2 phi / d phi; phi_ij = dm2_ij q):
+//   dP/d dm21 = q (-A T21 + B2 T32)
+//   dP/d dm31 = -q (B1 T31 + B2 T32)
+//   dP/d s12  = -dA12 S21 - B (S32 - S31),   dA12 = 4 (1 - 2 s12) (1-s13)^2
+//   dP/d s13  = -dA13 S21 - dB13 ((1-s12) S31 + s12 S32),
+//               dA13 = -8 s12 (1-s12) (1-s13),  dB13 = 4 (1 - 2 s13)
+template <class R>
+struct PeeCoef {
+  double dm21, dm31, dm32;
+  R K0, A, B, B1, B2, s12, c12, dA12, dA13, dB13;
+  bool bad;
+};
+
+template <class R>
+__device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
+  PeeCoef<R> k;
+  k.dm21 = th[0];
+  k.dm31 = th[1];
+  k.dm32 = th[1] - th[0];
+  const double s12 = th[2], s13 = th[3];
+  k.bad = !(s12 >= 0.0 && s12 <= 1.0 && s13 >= 0.0 && s13 <= 1.0);
+  const double c13 = 1.0 - s13, c12 = 1.0 - s12;
+  const double A = 4.0 * s12 * c12 * (c13 * c13);
+  const double B = 4.0 * s13 * c13;
+  k.K0 = to_r<R>(1.0 - A - B);
+  k.A = to_r<R>(A);
+  k.B = to_r<R>(B);
+  k.B1 = to_r<R>(B * c12);
+  k.B2 = to_r<R>(B * s12);
+  k.s12 = to_r<R>(s12);
+  k.c12 = to_r<R>(c12);
+  k.dA12 = to_r<R>(4.0 * (1.0 - 2.0 * s12) * (c13 * c13));
+  k.dA13 = to_r<R>(-8.0 * s12 * c12 * c13);
+  k.dB13 = to_r<R>(4.0 * (1.0 - 2.0 * s13));
+  return k;
+}
+
+// P_ee and its four parameter derivatives at phase-per-eV^2 q = (K L) / E.
+template <class R, bool GRAD>
+__device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R dP[4]) {
+  const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
+  const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
+  const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
+  R p = k.K0;
+  p = p + k.A * t21.C;
+  p = p + k.B1 * t31.C;
+  p = p + k.B2 * t32.C;
+  P = p;
+  if (GRAD) {
+    const R qr = to_r<R>(q);
+    dP[0] = qr * (k.B2 * t32.T - k.A * t21.T);
+    dP[1] = -qr * (k.B1 * t31.T + k.B2 * t32.T);
+    dP[2] = -(k.dA12 * t21.S) - k.B * (t32.S - t31.S);
+    dP[3] = -(k.dA13 * t21.S) - k.dB13 * (k.c12 * t31.S + k.s12 * t32.S);
+  }
+}
+
+}  // namespace gna

@@ -1,0 +1,171 @@
+// Elementwise survival probability over a resident energy vector (Sec. 4.1):
+// P[i] = sum_r w_r P_ee(E[i]; L_r, theta).
+//
+// HBM-streaming kernel: 16-byte non-temporal loads of two energies per lane
+// and 16-byte (FP64) or 8-byte (mixed) stores; the probability needs only
+// cos^2 of each phase, so one sin^2 polynomial per phase is evaluated
+// (cos^2 = 1 - sin^2 >= 1/2 on the reduced argument).  Phases and their
+// reduction are FP64 in both modes.
+#include <cmath>
+
+#include "gna_internal.h"
+#include "gna_math.h"
+
+namespace gna {
+namespace {
+
+constexpr int kPeeThreads = 256;
+
+template <class R>
+struct PeeArgs {
+  R K0, A, B1, B2;
+  double dm21, dm31, dm32;
+  int32_t n_L;
+  double KL[kMaxBaselines];  // K * L_r, rounded once (the q = (K L) / E order)
+  R w[kMaxBaselines];
+};
+
+template <class R, bool ONE_L>
+__device__ __forceinline__ R pee_eval(const PeeArgs<R>& a, double E) {
+  R acc = R(0);
+  const int nL = ONE_L ? 1 : a.n_L;
+  for (int r = 0; r < nL; ++r) {
+    const double q = a.KL[r] / E;
+    const R c21 = cos2_phase<R>(a.dm21 * q);
+    const R c31 = cos2_phase<R>(a.dm31 * q);
+    const R c32 = cos2_phase<R>(a.dm32 * q);
+    R p = a.K0;
+    p = p + a.A * c21;
+    p = p + a.B1 * c31;
+    p = p + a.B2 * c32;
+    acc = ONE_L ? p : acc + a.w[r] * p;
+  }
+  return E > 0.0 ? acc : R(NAN);
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
+template <class R>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using T = dvec2;
+};
+template <>
+struct Vec2<float> {
+  using T = fvec2;
+};
+
+// Each lane handles pairs p = tid, tid + stride, ...; two pairs per trip keep
+// two independent streams of FP64 work in flight per lane.
+template <class R, bool ONE_L>
+__global__ void __launch_bounds__(kPeeThreads)
+    pee_kernel(const double* __restrict__ E, int64_t n, PeeArgs<R> a, R* __restrict__ P) {
+  using V = typename Vec2<R>::T;
+  const int64_t npairs = n >> 1;
+  const int64_t stride = (int64_t)gridDim.x * kPeeThreads;
+  int64_t p = (int64_t)blockIdx.x * kPeeThreads + threadIdx.x;
+  const dvec2* E2 = reinterpret_cast<const dvec2*>(E);
+  V* P2 = reinterpret_cast<V*>(P);
+  for (; p + stride < npairs; p += 2 * stride) {
+    const dvec2 e0 = __builtin_nontemporal_load(E2 + p);
+    const dvec2 e1 = __builtin_nontemporal_load(E2 + p + stride);
+    V o0, o1;
+    o0.x = pee_eval<R, ONE_L>(a, e0.x);
+    o0.y = pee_eval<R, ONE_L>(a, e0.y);
+    o1.x = pee_eval<R, ONE_L>(a, e1.x);
+    o1.y = pee_eval<R, ONE_L>(a, e1.y);
+    __builtin_nontemporal_store(o0, P2 + p);
+    __builtin_nontemporal_store(o1, P2 + p + stride);
+  }
+  if (p < npairs) {
+    const dvec2 e0 = __builtin_nontemporal_load(E2 + p);
+    V o0;
+    o0.x = pee_eval<R, ONE_L>(a, e0.x);
+    o0.y = pee_eval<R, ONE_L>(a, e0.y);
+    __builtin_nontemporal_store(o0, P2 + p);
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) P[n - 1] = pee_eval<R, ONE_L>(a, E[n - 1]);
+}
+
+int g_cu_count = 0;
+
+int cu_count() {
+  if (g_cu_count > 0) return g_cu_count;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  g_cu_count = cus;
+  return cus;
+}
+
+template <class R>
+int run_pee(const double* E, int64_t n, int32_t n_L, const double* L, const double* wL,
+            const double* th, void* P, hipStream_t s) {
+  PeeArgs<R> a{};
+  const double s12 = th[2], s13 = th[3];
+  const double c12 = 1.0 - s12, c13 = 1.0 - s13;
+  const double A = 4.0 * s12 * c12 * (c13 * c13);
+  const double B = 4.0 * s13 * c13;
+  a.K0 = (R)(1.0 - A - B);
+  a.A = (R)A;
+  a.B1 = (R)(B * c12);
+  a.B2 = (R)(B * s12);
+  a.dm21 = th[0];
+  a.dm31 = th[1];
+  a.dm32 = th[1] - th[0];
+  a.n_L = n_L;
+  for (int r = 0; r < n_L; ++r) {
+    a.KL[r] = kPhase * L[r];
+    a.w[r] = (R)(wL ? wL[r] : 1.0 / n_L);
+  }
+  const int64_t npairs = n >> 1;
+  const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
+  const int64_t cap = (int64_t)cu_count() * 16;  // 16 resident groups of 4 waves per CU
+  const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
+  const bool oneL = (n_L == 1 && (!wL || wL[0] == 1.0));
+  if (oneL)
+    hipLaunchKernelGGL((pee_kernel<R, true>), dim3(blocks), dim3(kPeeThreads), 0, s, E, n, a,
+                       (R*)P);
+  else
+    hipLaunchKernelGGL((pee_kernel<R, false>), dim3(blocks), dim3(kPeeThreads), 0, s, E, n, a,
+                       (R*)P);
+  return check_hip(hipGetLastError(), "gna_pee launch");
+}
+
+}  // namespace
+}  // namespace gna
+
+extern "C" int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double* L_km_host,
+                       const double* wL_host, const double* theta_host, void* P_dev,
+                       int32_t prec, void* stream) {
+  using namespace gna;
+  clear_error();
+  if (n < 0) return fail(GNA_E_INVAL, "gna_pee: n = %lld < 0", (long long)n);
+  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "gna_pee: bad prec %d", prec);
+  if (n_L < 1 || n_L > kMaxBaselines)
+    return fail(GNA_E_INVAL, "gna_pee: n_L = %d outside 1..%d", n_L, kMaxBaselines);
+  if (!L_km_host || !theta_host) return fail(GNA_E_INVAL, "gna_pee: NULL L or theta");
+  for (int r = 0; r < n_L; ++r)
+    if (!(L_km_host[r] >= 0.0) || !std::isfinite(L_km_host[r]))
+      return fail(GNA_E_INVAL, "gna_pee: baseline %d = %g is not a finite value >= 0", r,
+                  L_km_host[r]);
+  const double s12 = theta_host[2], s13 = theta_host[3];
+  if (!(s12 >= 0.0 && s12 <= 1.0 && s13 >= 0.0 && s13 <= 1.0))
+    return fail(GNA_E_INVAL, "gna_pee: s12 = %g, s13 = %g must lie in [0, 1]", s12, s13);
+  if (!std::isfinite(theta_host[0]) || !std::isfinite(theta_host[1]))
+    return fail(GNA_E_INVAL, "gna_pee: dm2 not finite");
+  if (n == 0) return GNA_OK;
+  if (!E_dev || !P_dev) return fail(GNA_E_INVAL, "gna_pee: NULL device pointer");
+  if (((uintptr_t)E_dev & 15) != 0) return fail(GNA_E_INVAL, "gna_pee: E_dev not 16-byte aligned");
+  const uintptr_t palign = (prec == GNA_FP64) ? 15 : 7;
+  if (((uintptr_t)P_dev & palign) != 0)
+    return fail(GNA_E_INVAL, "gna_pee: P_dev not %d-byte aligned", (int)palign + 1);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == GNA_FP64)
+    return run_pee<double>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
+  return run_pee<float>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
+}

@@ -1,0 +1,34 @@
+"""Shared helpers of the GPU parity tests (inputs come from workloads, expected
+values from the oracle only)."""
+import numpy as np
+
+import oracle
+import workloads as W
+
+# FP64 parity bound of the method (spec: 1e-12 relative).
+FP64_RTOL = 1e-12
+
+
+def with_data(problem, model, seed, theta=None):
+    """Attach Poisson pseudo-data drawn from the oracle's prediction at theta."""
+    pr = dict(problem)
+    nu = oracle.prediction(pr, model, W.THETA0 if theta is None else theta)
+    pr["data"] = W.poisson_counts(nu, seed)
+    return pr
+
+
+def grad_error(g, g_ref, theta, chi2_ref):
+    """Per-component gradient error in chi^2 units per unit relative change of
+    the parameter, relative to max(|theta_c g_c|, chi2, 1): the gradient is
+    ~0 near a minimum, so a plain relative error is meaningless there."""
+    g = np.atleast_2d(g)
+    g_ref = np.atleast_2d(g_ref)
+    th = np.atleast_2d(theta)
+    scale = np.maximum(np.maximum(np.abs(th * g_ref), np.atleast_1d(chi2_ref)[:, None]), 1.0)
+    return np.abs(th * (g - g_ref)) / scale
+
+
+def rel_err(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return np.abs(x - ref) / np.maximum(np.abs(ref), 1e-300)

@@ -1,0 +1,132 @@
+"""The C-ABI library loads and exports what include/gna_hip.h declares.
+
+CPU-only: no call here touches the GPU (workspace sizing and argument
+validation run entirely on the host, before any HIP call).
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gna_hip.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gna_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1804_07682_amd import _lib
+    if not os.path.exists(_lib.LIBPATH):
+        pytest.fail("libgna_hip.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("gna_pee", "gna_chain_create", "gna_chain_eval", "gna_fitset_eval",
+                 "gna_plan_status", "gna_plan_autotune", "gna_gl_nodes", "gna_plan_tables"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1804_07682_amd import _lib
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version_and_strings(lib):
+    assert lib.gna_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5, 17):
+        assert lib.gna_strerror(code)
+    assert lib.gna_strerror(-4).decode().startswith("workspace")
+
+
+def _pee_call(lib, **kw):
+    args = dict(E=C.c_void_p(16), n=4, nL=1, L=[52.5], w=None, th=[7.5e-5, 2.5e-3, 0.3, 0.02],
+                P=C.c_void_p(16), prec=0)
+    args.update(kw)
+    L = np.asarray(args["L"], dtype=np.float64)
+    th = np.asarray(args["th"], dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    return lib.gna_pee(args["E"], args["n"], args["nL"], L.ctypes.data_as(dp), None,
+                       th.ctypes.data_as(dp), args["P"], args["prec"], None)
+
+
+def test_pee_rejects_bad_arguments_on_the_host(lib):
+    assert _pee_call(lib, n=-1) == -1
+    assert _pee_call(lib, prec=7) == -1
+    assert _pee_call(lib, nL=0) == -1
+    assert _pee_call(lib, nL=65) == -1
+    assert _pee_call(lib, th=[7.5e-5, 2.5e-3, 1.5, 0.02]) == -1
+    assert _pee_call(lib, th=[7.5e-5, 2.5e-3, 0.3, -0.1]) == -1
+    assert _pee_call(lib, L=[-1.0]) == -1
+    assert _pee_call(lib, E=C.c_void_p(8)) == -1  # misaligned
+    assert _pee_call(lib, E=None) == -1
+    assert b"aligned" in lib.gna_last_error_message() or b"NULL" in lib.gna_last_error_message()
+    assert _pee_call(lib, n=0, E=None, P=None) == 0  # empty input is a no-op
+
+
+def _sizes(lib, problem, prec=0, B=1, opts=None):
+    from paper_1804_07682_amd import api
+    keep = []
+    m = api.make_model(W.model())
+    p = api.make_problem(problem, keep)
+    o = api.make_opts(opts)
+    n = C.c_size_t(0)
+    st = lib.gna_chain_workspace_size(C.byref(m), C.byref(p), prec, B, C.byref(o) if o else None,
+                                      C.byref(n))
+    return st, n.value
+
+
+def test_workspace_sizing_is_host_only_and_scales(lib):
+    pr = W.config0()
+    pr["data"] = np.ones(240)
+    st, n1 = _sizes(lib, pr, B=1)
+    assert st == 0 and n1 > 0
+    st, n2 = _sizes(lib, pr, B=4096)
+    assert st == 0 and n2 > n1
+    st, m1 = _sizes(lib, pr, prec=1, B=1)
+    assert st == 0 and m1 < n1  # FP32 tables in mixed mode
+    pr2 = W.config2()
+    pr2["data"] = np.ones(240)
+    st, n3 = _sizes(lib, pr2, B=1)
+    assert st == 0 and n3 > n1
+
+
+def test_chain_validation_errors(lib):
+    pr = W.config0()
+    pr["data"] = np.ones(240)
+    bad = dict(pr, edges=pr["edges"][::-1].copy())
+    assert _sizes(lib, bad)[0] == -1
+    bad = dict(pr, gl_order=0)
+    assert _sizes(lib, bad)[0] == -1
+    bad = dict(pr, gl_order=65)
+    assert _sizes(lib, bad)[0] == -1
+    d = np.ones(240)
+    d[3] = -1.0
+    assert _sizes(lib, dict(pr, data=d))[0] == -1
+    assert _sizes(lib, pr, prec=3)[0] == -1
+    assert _sizes(lib, pr, B=0)[0] == -1
+    assert _sizes(lib, pr, opts={"threads": 100})[0] == -1
+    assert _sizes(lib, pr, opts={"lanes_per_bin": 3})[0] == -1
+    big = W.problem(W.uniform_edges(5000), 3, [52.5])
+    big["data"] = np.ones(5000)
+    assert _sizes(lib, big)[0] == -1
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1804_07682_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIBPATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.load()

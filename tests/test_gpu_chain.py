@@ -1,0 +1,211 @@
+"""GPU parity of the fused chain (gna_chain_*) against the oracle.
+
+Every expected value is the oracle's, on inputs from ``workloads``.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.helpers import FP64_RTOL, grad_error, rel_err, with_data
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+MODEL = W.model()
+
+# Mixed-precision bounds (FP32 point pass, bin sums and smearing; FP64 chi^2).
+MIXED_PRED_RTOL = 2e-6
+MIXED_CHI2_RTOL = 1e-5
+MIXED_GRAD_TOL = 1e-4
+
+
+def _plan(problem, B=1, prec="fp64", **opts):
+    import paper_1804_07682_amd as gna
+    o = dict(opts) if opts else None
+    return gna.Chain(problem, MODEL, max_batch=B, prec=prec, opts=o, device=DEV)
+
+
+def _eval(plan, P, pred=True):
+    Pt = torch.tensor(np.atleast_2d(P), dtype=torch.float64, device=DEV)
+    out = plan.eval(Pt, grad=True, pred=pred)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return with_data(W.config0(), MODEL, W.SEED)
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return with_data(W.config2(), MODEL, W.SEED + 2)
+
+
+THETAS = [W.THETA0, W.THETA0 * np.array([1.03, 0.98, 1.05, 0.9, 1.02])]
+
+
+def _check_fp64(got, ref, P):
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+
+
+@pytest.mark.parametrize("ti", range(len(THETAS)))
+def test_cfg0_fp64_single_tile(cfg0, ti):
+    P = np.atleast_2d(THETAS[ti])
+    plan = _plan(cfg0, smear_mfma=0)
+    assert plan.shape()["n_tiles"] == 1
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True)
+    _check_fp64(got, ref, P)
+    assert plan.status() == 0
+
+
+@pytest.mark.parametrize("opts", [
+    dict(threads=64, lanes_per_bin=1, chunks=1),   # 4 bin blocks -> last-tile hand-off
+    dict(threads=64, lanes_per_bin=4, chunks=5),   # 15 blocks x 5 chunks
+    dict(threads=128, lanes_per_bin=2, chunks=3),
+    dict(threads=256, lanes_per_bin=8, chunks=2, persistent=1),
+    dict(threads=512, lanes_per_bin=1, chunks=1),
+])
+def test_cfg0_fp64_multi_tile_shapes(cfg0, opts):
+    P = np.atleast_2d(THETAS[1])
+    plan = _plan(cfg0, smear_mfma=0, **opts)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True)
+    for _ in range(3):  # counters and queue reset themselves between launches
+        got = _eval(plan, P)
+        _check_fp64(got, ref, P)
+
+
+def test_cfg0_mixed(cfg0):
+    P = np.atleast_2d(THETAS[1])
+    plan = _plan(cfg0, prec="mixed", smear_mfma=0)
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True)
+    e_pred = np.max(rel_err(got["pred"], ref["nu"]))
+    e_chi2 = np.max(rel_err(got["chi2"], ref["chi2"]))
+    e_grad = np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"]))
+    print(f"cfg0 mixed: pred {e_pred:.2e} chi2 {e_chi2:.2e} grad {e_grad:.2e}")
+    assert e_pred <= MIXED_PRED_RTOL
+    assert e_chi2 <= MIXED_CHI2_RTOL
+    assert e_grad <= MIXED_GRAD_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cfg2_full_chain(cfg2, prec):
+    P = np.atleast_2d(THETAS[1])
+    plan = _plan(cfg2, prec=prec, smear_mfma=0)
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg2, MODEL, P, grad=True, nu=True)
+    if prec == "fp64":
+        _check_fp64(got, ref, P)
+    else:
+        e = np.max(rel_err(got["pred"], ref["nu"]))
+        print(f"cfg2 mixed pred {e:.2e}")
+        assert e <= MIXED_PRED_RTOL
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= MIXED_CHI2_RTOL
+        assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= MIXED_GRAD_TOL
+
+
+def test_batch_matches_single_points_and_oracle(cfg0):
+    P = W.config3_params(8, 8)
+    plan = _plan(cfg0, B=64, smear_mfma=0)
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
+    _check_fp64(got, ref, P)
+    one = _plan(cfg0, B=1, smear_mfma=0)
+    for b in (0, 17, 63):
+        g1 = _eval(one, P[b])
+        assert g1["chi2"][0] == got["chi2"][b]
+        assert np.array_equal(g1["grad"][0], got["grad"][b])
+
+
+def test_deterministic(cfg2):
+    P = np.atleast_2d(THETAS[1])
+    plan = _plan(cfg2, smear_mfma=0)
+    a = _eval(plan, P)
+    b = _eval(plan, P)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_exact_data_gives_zero(cfg0):
+    """Feeding the library its own prediction as data: chi^2 = 0, gradient = 0."""
+    plan = _plan(cfg0, smear_mfma=0)
+    nu = _eval(plan, W.THETA0)["pred"][0]
+    pr = dict(cfg0, data=nu)
+    plan2 = _plan(pr, smear_mfma=0)
+    got = _eval(plan2, W.THETA0)
+    assert got["chi2"][0] == 0.0
+    assert np.all(got["grad"][0] == 0.0)
+
+
+def test_tables_match_oracle(cfg2):
+    plan = _plan(cfg2, smear_mfma=0)
+    E, f, R = (t.cpu().numpy() for t in plan.tables())
+    Eo, wo = oracle.quadrature(cfg2["edges"], 5, 84)
+    assert np.max(np.abs(E - Eo) / Eo) <= 2.3e-16  # <= 1 ulp
+    fo = oracle.flux_xsec(Eo, wo, MODEL)
+    assert np.max(np.abs(f - fo)) <= 1e-14 * np.max(fo)
+    Ro = oracle.smearing(cfg2["edges"], MODEL["res_a"])
+    assert np.max(np.abs(R - Ro)) <= 2e-16
+
+
+def test_gl_nodes_match_oracle():
+    import paper_1804_07682_amd as gna
+    for n in (1, 2, 3, 5, 10, 17, 64):
+        t, w = (x.cpu().numpy() for x in gna.gna_gl_nodes(n))
+        to, wo = oracle.gauss_legendre(n)
+        assert np.max(np.abs(t - to)) <= 2.3e-16
+        assert np.max(np.abs(w - wo) / wo) <= 64 * 2.3e-16
+
+
+def test_domain_errors_latch(cfg0):
+    import paper_1804_07682_amd as gna
+    plan = _plan(cfg0, B=2, smear_mfma=0)
+    P = np.vstack([W.THETA0, W.THETA0])
+    P[1, 2] = 1.5
+    got = _eval(plan, P)
+    assert np.isfinite(got["chi2"][0]) and np.isnan(got["chi2"][1])
+    with pytest.raises(gna.GnaError):
+        plan.status()
+    assert plan.status() == 0  # cleared by the read
+    P = np.atleast_2d(W.THETA0.copy())
+    P[0, 4] = 0.0  # nu = 0
+    _eval(plan, P)
+    with pytest.raises(gna.GnaError):
+        plan.status()
+
+
+def test_autograd_function(cfg0):
+    import paper_1804_07682_amd as gna
+    plan = _plan(cfg0, B=3, smear_mfma=0)
+    P = torch.tensor(np.vstack(THETAS + [W.THETA0 * 1.01]), dtype=torch.float64, device=DEV,
+                     requires_grad=True)
+    c = gna.chi2(P, plan)
+    w = torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device=DEV)
+    (c * w).sum().backward()
+    ref = oracle.chain(cfg0, MODEL, P.detach().cpu().numpy(), grad=True)
+    expect = w.cpu().numpy()[:, None] * ref["grad"]
+    assert np.max(np.abs(P.grad.cpu().numpy() - expect) / (np.abs(expect) + 1e-300)) <= 1e-10
+
+
+def test_adjoint_vs_central_differences(cfg0):
+    plan = _plan(cfg0, B=11, smear_mfma=0)
+    th = THETAS[1]
+    P = [th]
+    for c in range(5):
+        h = 1e-6 * abs(th[c])
+        for sgn in (1, -1):
+            t = th.copy()
+            t[c] += sgn * h
+            P.append(t)
+    got = _eval(plan, np.array(P), pred=False)
+    g = got["grad"][0]
+    for c in range(5):
+        h = 1e-6 * abs(th[c])
+        fd = (got["chi2"][1 + 2 * c] - got["chi2"][2 + 2 * c]) / (2 * h)
+        assert abs(fd - g[c]) * abs(th[c]) <= 1e-6 * max(abs(g[c] * th[c]), got["chi2"][0])

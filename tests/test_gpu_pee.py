@@ -1,0 +1,102 @@
+"""GPU parity of the elementwise survival probability (gna_pee) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.helpers import FP64_RTOL, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TH = W.THETA0
+DEV = "cuda"
+
+# Mixed precision: every cos^2 term carries <= ~4 FP32 ulps and the 4-term
+# all-positive sum adds 3 roundings, so |dP| <= 8 u32 (K0 + A + B1 + B2) with
+# K0 + A + B1 + B2 = 1: an absolute bound of 8 * 2^-24 = 4.8e-7.
+MIXED_ATOL = 8 * 2.0 ** -24
+
+
+def _run(E, L, theta=TH, wL=None, prec="fp64"):
+    import paper_1804_07682_amd as gna
+    Et = torch.from_numpy(E).to(DEV)
+    out = gna.gna_pee(Et, L, theta, wL=wL, prec=prec)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 257, 65536 + 129, 1_000_003])
+@pytest.mark.parametrize("L", W.CONFIG1_BASELINES)
+def test_pee_fp64_parity(n, L):
+    E = W.config1_energies(n)
+    got = _run(E, L)
+    ref = oracle.pee(E, L, TH, n_threads=8)
+    assert np.max(rel_err(got, ref)) <= FP64_RTOL
+
+
+@pytest.mark.parametrize("L", W.CONFIG1_BASELINES)
+def test_pee_mixed_error_bound(L):
+    E = W.config1_energies(1_000_003)
+    got = _run(E, L, prec="mixed")
+    ref = oracle.pee(E, L, TH, n_threads=8)
+    err = np.abs(got - ref)
+    assert np.max(err) <= MIXED_ATOL
+    print(f"mixed L={L}: max abs {err.max():.3e}, max rel {np.max(err / ref):.3e}")
+
+
+def test_pee_multi_baseline_weights():
+    E = W.config1_energies(100_001)
+    L = np.linspace(50, 55, 8)
+    w = np.linspace(1, 2, 8)
+    w /= w.sum()
+    got = _run(E, L, wL=w)
+    ref = oracle.pee(E, L, TH, wL=w, n_threads=8)
+    assert np.max(rel_err(got, ref)) <= FP64_RTOL
+    got = _run(E, L)  # default weights 1/n_L
+    ref = oracle.pee(E, L, TH, n_threads=8)
+    assert np.max(rel_err(got, ref)) <= FP64_RTOL
+
+
+def test_pee_degenerate_cases():
+    E = W.config1_energies(10_001)
+    assert np.all(_run(E, 0.0) == 1.0)
+    th = TH.copy()
+    th[0] = th[1] = 0.0
+    assert np.all(_run(E, 52.5, th) == 1.0)
+    th = TH.copy()
+    th[3] = 0.0  # two-flavour limit
+    ref = oracle.pee(E, 52.5, th)
+    assert np.max(rel_err(_run(E, 52.5, th), ref)) <= FP64_RTOL
+    # Non-positive energies give NaN in their slot only.
+    E2 = E[:6].copy()
+    E2[1] = 0.0
+    E2[4] = -3.0
+    got = _run(E2, 52.5)
+    assert np.isnan(got[1]) and np.isnan(got[4])
+    assert np.all(np.isfinite(got[[0, 2, 3, 5]]))
+
+
+def test_pee_empty_and_errors():
+    import paper_1804_07682_amd as gna
+    E = torch.empty(0, dtype=torch.float64, device=DEV)
+    assert gna.gna_pee(E, 52.5, TH).numel() == 0
+    E = torch.ones(8, dtype=torch.float64, device=DEV)
+    with pytest.raises(gna.GnaError):
+        gna.gna_pee(E, 52.5, [7.5e-5, 2.5e-3, 1.2, 0.02])
+    with pytest.raises(gna.GnaError):
+        gna.gna_pee(E[1:], 52.5, TH)  # misaligned view
+
+
+def test_pee_full_size_sampled():
+    """N = 1e8 at the benchmark's launch shape, sampled against the oracle."""
+    n = 10 ** 8
+    E = W.config1_energies(n)
+    idx = np.random.default_rng(5).integers(0, n, 200_000)
+    idx[:4] = [0, 1, n - 2, n - 1]
+    for L in W.CONFIG1_BASELINES:
+        got = _run(E, L)
+        ref = oracle.pee(E[idx], L, TH, n_threads=8)
+        assert np.max(rel_err(got[idx], ref)) <= FP64_RTOL
+        gotm = _run(E, L, prec="mixed")
+        assert np.max(np.abs(gotm[idx] - ref)) <= MIXED_ATOL

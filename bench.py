@@ -1,0 +1,310 @@
+"""Benchmark of the GNA hot path on one MI355X.
+
+A step is one evaluation of the whole chain -- P_ee, flux x cross section,
+Gauss-Legendre bin integration, smearing, Poisson chi^2 and its 5-component
+gradient -- for the batched scan: 4096 parameter points on a 64 x 64 grid in
+(dm2_31, sin^2 th13), 240 bins x 5 Gauss-Legendre nodes (1200 points), one
+52.5 km baseline, mixed precision.  `value` is chi^2+gradient evaluations per
+second (parameter points per second), inputs resident in HBM.
+
+The same JSON line also carries, measured in this run:
+  * fp64: the same scan in plain FP64;
+  * pee: elementwise P_ee over N = 1e8 energies (52.5 km) in FP64 and mixed,
+    evaluations/s and HBM bandwidth against 8 TB/s;
+  * chain_1pt / chain_8L / fitset: the single-point chain (1200 points), the
+    single-point chain with 8 baselines and 100 800 points, and the uneven
+    batch of 1024 fits (evaluations/s, FP64 and mixed);
+  * mixed_vs_fp64: max errors of the mixed scan against FP64 per output;
+  * roofline of the dominant kernel, cpu_baseline of the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# Vector ALU peak with unpacked FP32/FP64 FMAs: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 flops x 2.4 GHz = 78.6 TFLOP/s (the kernels are built without packed FP32).
+ALU_PEAK_TFLOPS = 78.6
+# Algorithmic flops of one (point, baseline, parameter point) evaluation of P_ee
+# and its 4 tangents, with the FMA counted as 2 (see the roofline section of the
+# design notes): q = KL/E (2), 3 phases (3), per phase reduction + sin/cos
+# kernels + squares (43 x 3), P (6), tangents (18), baseline weight (10),
+# flux factor (10).
+FLOPS_PER_PEE_GRAD_EVAL = 178
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--only", default=None,
+                    help="run one workload for profiling: scan|scan64|pee|pee64|chain1|chain8|fitset")
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on the stream the library launches on (torch's current stream)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        k = np.array([a.elapsed_time(b) for a, b in ev]) * 1e-3
+        return wall, float(k.mean()), float(np.median(k))
+
+
+def scan_setup(gna, W, torch, prec, dev):
+    model = W.model()
+    pr = W.config0()
+    # Pseudo-data: Poisson counts drawn from this library's own FP64 prediction.
+    tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
+    nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
+                  pred=True)["pred"].cpu().numpy()[0]
+    pr["data"] = W.poisson_counts(nu, W.SEED)
+    P = torch.tensor(W.config3_params(), dtype=torch.float64, device=dev)
+    plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev)
+    return pr, model, plan, P
+
+
+def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup):
+    pr, model, plan, P = scan_setup(gna, W, torch, prec, dev)
+    out = {"chi2": torch.empty(P.shape[0], dtype=torch.float64, device=dev),
+           "grad": torch.empty((P.shape[0], 5), dtype=torch.float64, device=dev)}
+    fn = lambda: plan.eval(P, grad=True, out=out)
+    wall, kmean, kmed = timer.run(fn, steps, warmup)
+    plan.status()
+    return {"plan": plan, "pr": pr, "P": P, "wall": wall, "kernel_s": kmean, "kernel_med_s": kmed,
+            "evals_per_s": P.shape[0] * steps / wall, "shape": plan.shape()}
+
+
+def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
+    E = torch.from_numpy(W.config1_energies(n)).to(dev)
+    odt = torch.float64 if prec == "fp64" else torch.float32
+    out = torch.empty(n, dtype=odt, device=dev)
+    fn = lambda: gna.gna_pee(E, L, W.THETA0, prec=prec, out=out)
+    wall, kmean, _ = timer.run(fn, steps, 3)
+    nbytes = n * (8 + out.element_size())
+    res = {"evals_per_s": n * steps / wall, "kernel_ms": kmean * 1e3,
+           "GBps": nbytes / kmean / 1e9, "bytes_per_eval": 8 + out.element_size()}
+    res["hbm_frac"] = res["GBps"] / HBM_PEAK_GBPS
+    del E, out
+    return res
+
+
+def copy_probe(torch, timer, dev, n=10 ** 8):
+    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    wall, kmean, _ = timer.run(lambda: b.copy_(a), 10, 3)
+    return {"GBps": 16 * n / kmean / 1e9, "bytes": 16 * n}
+
+
+def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec):
+    model = W.model()
+    pr = problem_fn()
+    tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
+    nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
+                  pred=True)["pred"].cpu().numpy()[0]
+    pr["data"] = W.poisson_counts(nu, seed)
+    plan = gna.Chain(pr, model, max_batch=1, prec=prec, device=dev)
+    P = torch.tensor(W.THETA0 * np.array([1.01, 0.99, 1.02, 0.97, 1.0]),
+                     device=dev).reshape(1, 5)
+    plan.autotune(P, reps=5)
+    out = {"chi2": torch.empty(1, dtype=torch.float64, device=dev),
+           "grad": torch.empty((1, 5), dtype=torch.float64, device=dev)}
+    wall, kmean, _ = timer.run(lambda: plan.eval(P, grad=True, out=out), steps, 10)
+    return {"evals_per_s": steps / wall, "kernel_us": kmean * 1e6, "shape": plan.shape()}
+
+
+def bench_fitset(gna, W, torch, timer, dev, steps, prec):
+    model = W.model()
+    problems, params = W.config4()
+    # Pseudo-data per fit from this library's FP64 prediction at THETA0.
+    tmp = gna.FitSet(problems, model, prec="fp64", device=dev)
+    th0 = torch.tensor(np.tile(W.THETA0, (len(problems), 1)), device=dev)
+    nu = tmp.eval(th0, grad=False, pred=True)["pred"].cpu().numpy()
+    del tmp
+    off = 0
+    for f, pb in enumerate(problems):
+        nb = len(pb["edges"]) - 1
+        pb["data"] = W.poisson_counts(nu[off:off + nb], W.config4_data_seed(f))
+        off += nb
+    plan = gna.FitSet(problems, model, prec=prec, device=dev)
+    P = torch.tensor(params, device=dev)
+    plan.autotune(P, reps=3)
+    wall, kmean, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
+    return {"fits_per_s": len(problems) * steps / wall, "kernel_ms": kmean * 1e3,
+            "shape": plan.shape()}
+
+
+def mixed_errors(gna, W, torch, dev, pr, P):
+    model = W.model()
+    res = {}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev)
+        outs[prec] = {k: v.cpu().numpy() for k, v in plan.eval(P, grad=True, pred=True).items()}
+    a, b = outs["mixed"], outs["fp64"]
+    res["pred_max_rel"] = float(np.max(np.abs(a["pred"] - b["pred"]) / np.abs(b["pred"])))
+    res["chi2_max_rel"] = float(np.max(np.abs(a["chi2"] - b["chi2"]) / np.abs(b["chi2"])))
+    res["chi2_max_abs"] = float(np.max(np.abs(a["chi2"] - b["chi2"])))
+    th = P.cpu().numpy()
+    scale = np.maximum(np.maximum(np.abs(th * b["grad"]), b["chi2"][:, None]), 1.0)
+    res["grad_max_scaled"] = float(np.max(np.abs(th * (a["grad"] - b["grad"])) / scale))
+    return res
+
+
+def cpu_baseline(W, pr_gpu):
+    """The oracle, as it stands, on the scan workload (its own pseudo-data)."""
+    import oracle
+    model = W.model()
+    pr = W.config0()
+    pr["data"] = W.poisson_counts(oracle.prediction(pr, model, W.THETA0), W.SEED)
+    P = W.config3_params()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    oracle.chain(pr, model, P[:64], grad=True, n_threads=threads)  # warm-up
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        oracle.chain(pr, model, P, grad=True, n_threads=threads)
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps >= 500:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": P.shape[0] * reps / dt, "unit": "chi2+grad evals/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} x the full 4096-point scan (1200 points, 240 bins), "
+                      f"{dt:.1f} s, OpenMP over parameter points"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the design notes describe how the scan would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1804_07682_amd as gna
+    import workloads as W
+    gna.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    timer = Timer(torch)
+
+    if args.only:
+        o = args.only
+        if o in ("scan", "scan64"):
+            r = bench_scan(gna, W, torch, timer, "fp64" if o == "scan64" else "mixed", dev,
+                           args.steps, args.warmup)
+            log(f"{o}: {r['evals_per_s']:.4g} evals/s kernel {r['kernel_s'] * 1e6:.1f} us "
+                f"shape {r['shape']}")
+        elif o in ("pee", "pee64"):
+            r = bench_pee(gna, W, torch, timer, dev, 10 ** 8, 52.5,
+                          "fp64" if o == "pee64" else "mixed", args.steps)
+            log(f"{o}: {r}")
+            log(f"copy probe: {copy_probe(torch, timer, dev)}")
+        elif o == "chain1":
+            log(str(bench_chain_single(gna, W, torch, timer, dev, W.config0, W.SEED, args.steps,
+                                       args.prec)))
+        elif o == "chain8":
+            log(str(bench_chain_single(gna, W, torch, timer, dev, W.config2, W.SEED + 2,
+                                       args.steps, args.prec)))
+        elif o == "fitset":
+            log(str(bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec)))
+        return
+
+    log("scan (mixed) ...")
+    torch.cuda.synchronize()
+    main_r = bench_scan(gna, W, torch, timer, "mixed", dev, args.steps, args.warmup)
+    B = main_r["P"].shape[0]
+    units = B * 1200  # (point, baseline, parameter) evaluations per launch
+    achieved = FLOPS_PER_PEE_GRAD_EVAL * units / main_r["kernel_s"] / 1e12
+    line = {
+        "metric": "chi2+grad evals/s (batched scan, mixed precision; P_ee evals/s in pee)",
+        "value": main_r["evals_per_s"],
+        "unit": "chi2+grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["wall"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "batched scan: 4096 points (64x64 grid in dm2_31 x sin2th13), "
+                               "240 bins x 5-point Gauss-Legendre (1200 points), L=52.5 km, "
+                               "chi2 + 5-parameter adjoint gradient",
+                   "points": B, "bins": 240, "quadrature_points": 1200, "baselines": 1,
+                   "precision": "mixed (FP64 phases and reduction, FP32 elsewhere, FP64 chi2)",
+                   "shape": main_r["shape"]},
+        "pee_evals_per_s_per_chi2_eval": 1200,
+        "roofline": {"bound": "alu", "kernel": "fused chain kernel (scan)",
+                     "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel_us": main_r["kernel_s"] * 1e6,
+                     "flops_per_unit": FLOPS_PER_PEE_GRAD_EVAL, "units_per_launch": units},
+    }
+    if not args.quick:
+        log("scan (fp64) ...")
+        r64 = bench_scan(gna, W, torch, timer, "fp64", dev, args.steps, args.warmup)
+        line["fp64"] = {"value": r64["evals_per_s"], "kernel_us": r64["kernel_s"] * 1e6,
+                        "mixed_speedup": main_r["evals_per_s"] / r64["evals_per_s"],
+                        "shape": r64["shape"]}
+        log("mixed vs fp64 errors ...")
+        line["mixed_vs_fp64"] = mixed_errors(gna, W, torch, dev, main_r["pr"], main_r["P"])
+        log("pee N=1e8 ...")
+        pee = {}
+        for prec in ("fp64", "mixed"):
+            pee[prec] = bench_pee(gna, W, torch, timer, dev, 10 ** 8, 52.5, prec, 20)
+        pee["copy_probe"] = copy_probe(torch, timer, dev)
+        pee["workload"] = "N=1e8 energies uniform in [1.8, 12] MeV, L=52.5 km, one parameter point"
+        line["pee"] = pee
+        log("single-point chains ...")
+        line["chain_1pt"] = {p: bench_chain_single(gna, W, torch, timer, dev, W.config0, W.SEED,
+                                                   400, p) for p in ("fp64", "mixed")}
+        line["chain_8L"] = {p: bench_chain_single(gna, W, torch, timer, dev, W.config2,
+                                                  W.SEED + 2, 200, p) for p in ("fp64", "mixed")}
+        log("fitset ...")
+        line["fitset"] = {p: bench_fitset(gna, W, torch, timer, dev, 10, p)
+                          for p in ("fp64", "mixed")}
+    log("cpu baseline (oracle) ...")
+    line["cpu_baseline"] = cpu_baseline(W, main_r["pr"])
+    print(json.dumps(line, default=lambda o: o if not isinstance(o, np.generic) else o.item()),
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()

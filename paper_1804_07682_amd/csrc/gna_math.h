@@ -19,18 +19,33 @@ constexpr double kPhase = 1266.9326794198487;
 __device__ __forceinline__ double dfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// phi = m * pi/2 + r with |r| <= pi/4 (+ rounding), m = rint(phi * 2/pi).
-// Three-part Cody-Waite subtraction with FMAs: each step is one rounding of
-// an exactly formed product, so r carries ~1 ulp absolute error for
-// |m| < 2^52; `odd` is the parity of m (computed in FP64, no integer overflow).
+// phi = m * pi/2 + r with |r| <= pi/4 (+ rounding), m = nearest integer to
+// phi * 2/pi.  t = phi * 2/pi + 1.5 * 2^52 is rounded once by the FMA to an
+// integer held in the low mantissa bits, so m = t - 1.5 * 2^52 exactly and the
+// parity of m is bit 0 of t (valid for |phi| < 2^50).  Two-part Cody-Waite
+// subtraction with FMAs: each step rounds an exactly formed product once; the
+// dropped third part of pi/2 contributes |m| * 1.5e-33, far below an ulp of r.
 __device__ __forceinline__ double reduce_pio2(double phi, bool& odd) {
-  const double m = __builtin_rint(phi * GNA_TWO_OVER_PI);
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  const double t = dfma(phi, GNA_TWO_OVER_PI, magic);
+  const double m = t - magic;
+  odd = (__double2loint(t) & 1) != 0;
   double r = dfma(-m, GNA_PIO2_1, phi);
   r = dfma(-m, GNA_PIO2_2, r);
-  r = dfma(-m, GNA_PIO2_3, r);
-  const double h = m * 0.5;
-  odd = (h != __builtin_rint(h));
   return r;
+}
+
+// q = KL / E, correctly rounded (the IEEE division): FP64 phases are then
+// bit-identical to any other correctly rounded evaluation of (K L) / E.
+__device__ __forceinline__ double phase_per_ev2(double KL, double E) { return KL / E; }
+
+// q = KL / E within ~2 ulp: hardware reciprocal refined by two Newton steps
+// (mixed precision, where the phase needs ~1e-13 relative, not bit identity).
+__device__ __forceinline__ double phase_per_ev2_fast(double KL, double E) {
+  double y = __builtin_amdgcn_rcp(E);
+  y = dfma(y, dfma(-E, y, 1.0), y);
+  y = dfma(y, dfma(-E, y, 1.0), y);
+  return KL * y;
 }
 
 // sin r, cos r on |r| <= pi/4 (minimax kernels from trig_coeffs.h).
@@ -89,6 +104,11 @@ __device__ __forceinline__ float sin2_kernel(float r) {
 
 template <class R>
 __device__ __forceinline__ R to_r(double x) { return static_cast<R>(x); }
+
+__device__ __forceinline__ double rfma_t_impl(double a, double b, double c) { return dfma(a, b, c); }
+__device__ __forceinline__ float rfma_t_impl(float a, float b, float c) { return ffma(a, b, c); }
+template <class R>
+__device__ __forceinline__ R rfma_t(R a, R b, R c) { return rfma_t_impl(a, b, c); }
 
 // cos^2(phi) only (probability without tangents).  The reduction is FP64;
 // the kernel runs in R (double, or float for the mixed-precision mode).
@@ -171,10 +191,9 @@ __device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R
   const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
   const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
   const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
-  R p = k.K0;
-  p = p + k.A * t21.C;
-  p = p + k.B1 * t31.C;
-  p = p + k.B2 * t32.C;
+  R p = rfma_t<R>(k.A, t21.C, k.K0);
+  p = rfma_t<R>(k.B1, t31.C, p);
+  p = rfma_t<R>(k.B2, t32.C, p);
   P = p;
   if (GRAD) {
     const R qr = to_r<R>(q);

@@ -5,7 +5,8 @@
 // and 16-byte (FP64) or 8-byte (mixed) stores; the probability needs only
 // cos^2 of each phase, so one sin^2 polynomial per phase is evaluated
 // (cos^2 = 1 - sin^2 >= 1/2 on the reduced argument).  Phases and their
-// reduction are FP64 in both modes.
+// reduction are FP64 in both modes; FP64 mode divides q = KL / E exactly
+// (IEEE), mixed mode uses a refined reciprocal.
 #include <cmath>
 
 #include "gna_internal.h"
@@ -30,14 +31,13 @@ __device__ __forceinline__ R pee_eval(const PeeArgs<R>& a, double E) {
   R acc = R(0);
   const int nL = ONE_L ? 1 : a.n_L;
   for (int r = 0; r < nL; ++r) {
-    const double q = a.KL[r] / E;
+    const double q = (sizeof(R) == 8) ? phase_per_ev2(a.KL[r], E) : phase_per_ev2_fast(a.KL[r], E);
     const R c21 = cos2_phase<R>(a.dm21 * q);
     const R c31 = cos2_phase<R>(a.dm31 * q);
     const R c32 = cos2_phase<R>(a.dm32 * q);
-    R p = a.K0;
-    p = p + a.A * c21;
-    p = p + a.B1 * c31;
-    p = p + a.B2 * c32;
+    R p = rfma_t<R>(a.A, c21, a.K0);
+    p = rfma_t<R>(a.B1, c31, p);
+    p = rfma_t<R>(a.B2, c32, p);
     acc = ONE_L ? p : acc + a.w[r] * p;
   }
   return E > 0.0 ? acc : R(NAN);

@@ -1,34 +1,499 @@
-// Batched chain with the smearing on the matrix cores (filled in below).
+// Batched chain for one geometry and many parameter points, with the smearing
+// on the matrix cores.
+//
+// One work-group evaluates a tile of 16 parameter points over all bins:
+//   1. point pass: thread (bin group, point n) walks its bins' quadrature
+//      points and baselines (Sec. 4.1 probability and its tangents, q = KL/E
+//      and f_k staged in LDS) and keeps mu0_j and J0_jc in registers;
+//   2. nu = R mu as a block-banded GEMM [n_bins x n_bins] x [n_bins x 16]
+//      on 16x16x4 MFMA (FP32 accumulation in mixed mode, FP64 in FP64 mode);
+//      R is pre-tiled in MFMA operand order, so each A fetch is one
+//      contiguous 64-lane load, and all-zero 16x16 blocks are skipped;
+//   3. chi2 and gnu = d chi2 / d nu in FP64 from the accumulators;
+//   4. gmu = R^T gnu as a second block-banded GEMM;
+//   5. grad_c = norm sum_j gmu_j J0_jc, grad_norm = sum_j gmu_j mu0_j from
+//      the registers of step 1 (FP64 sums).
+// No global scratch and no inter-group hand-off: one launch, a persistent
+// grid over tiles.  Needs n_bins <= 256 and the q / f tables in LDS.
+#include <algorithm>
+#include <cmath>
+
 #include "gna_internal.h"
+#include "gna_math.h"
 
 namespace gna {
+namespace {
 
-bool scan_supported(const gna_plan* p) {
-  (void)p;
-  return false;
+constexpr int kScanN = 16;         // parameter points per tile (MFMA N)
+constexpr int kScanMaxBins = 256;  // 16 row tiles of 16
+constexpr size_t kScanLdsMax = 64 * 1024;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct Acc;
+// Operand layouts on gfx950 (checked with a one-hot probe of each builtin):
+// A[i][k] and B[k][j] sit in lane i + 16 k and lane j + 16 k for both
+// precisions; the 16x16 accumulator differs:
+//   f32: D[i][j] in lane j + 16 (i / 4), register i % 4  (row = 4 (lane/16) + v)
+//   f64: D[i][j] in lane j + 16 (i % 4), register i / 4  (row = lane/16 + 4 v)
+template <>
+struct Acc<float> {
+  using T = f32x4;
+  __device__ static T mfma(float a, float b, T c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int krow, int v) { return krow * 4 + v; }
+};
+template <>
+struct Acc<double> {
+  using T = f64x4;
+  __device__ static T mfma(double a, double b, T c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int krow, int v) { return krow + 4 * v; }
+};
+
+template <class R>
+struct ScanArgs {
+  int32_t B, nb, mt, ppb, nL, nq;
+  const double* qtab;  // [nL][nq]  q = (K L_r) / E_k
+  const R* f;          // [nq]
+  const double* wL;    // [nL]
+  const double* data;  // [nb]
+  const R* RA;         // [mt][mt][4][64]  R in A-operand order
+  const R* RT;         // [mt][mt][4][64]  R^T in A-operand order
+  const int32_t* kbA;  // [mt][2] first / last nonzero k-block of row tile
+  const int32_t* kbT;  // [mt][2]
+  const double* params;
+  double* chi2;
+  double* grad;
+  double* pred;
+  uint32_t* status;
+};
+
+__host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15); }
+
+template <class R>
+__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves) {
+  return a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
+         a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
+         a16((size_t)nwaves * kScanN * 6 * 8);
 }
 
-size_t scan_dense_bytes(const gna_plan* p) {
-  (void)p;
+template <class T>
+__device__ __forceinline__ T xor_sum_16_32(T v) {
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
+  return v;
+}
+
+template <class R, bool GRAD, int NT>
+__global__ void __launch_bounds__(NT) scan_kernel(ScanArgs<R> a) {
+  using A4 = typename Acc<R>::T;
+  constexpr int NW = NT / kWave;
+  constexpr int NG = NT / kScanN;           // bin groups
+  constexpr int PPT = kScanMaxBins / NG;    // bins per thread (upper bound)
+  constexpr int TPW = (16 + NW - 1) / NW;   // row tiles per wave (upper bound)
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int nL = a.nL, nq = a.nq, mt = a.mt, nb = a.nb, nbp = mt * 16;
+  unsigned char* cur = lds;
+  double* q_s = reinterpret_cast<double*>(cur);
+  cur += a16((size_t)nL * nq * 8);
+  R* f_s = reinterpret_cast<R*>(cur);
+  cur += a16((size_t)nq * sizeof(R));
+  double* d_s = reinterpret_cast<double*>(cur);
+  cur += a16((size_t)nbp * 8);
+  double* w_s = reinterpret_cast<double*>(cur);
+  cur += a16((size_t)nL * 8);
+  R* bb = reinterpret_cast<R*>(cur);  // [nbp][16] GEMM B operand
+  cur += a16((size_t)nbp * kScanN * sizeof(R));
+  double* red = reinterpret_cast<double*>(cur);  // [NW][16][6]
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nL * nq; i += NT) q_s[i] = a.qtab[i];
+  for (int i = tid; i < nq; i += NT) f_s[i] = a.f[i];
+  for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
+  for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
+  __syncthreads();
+
+  const int n = tid & (kScanN - 1);  // parameter point inside the tile (= GEMM column)
+  const int bg = tid >> 4;           // bin group
+  const int lane = tid & (kWave - 1), wave = tid >> 6;
+  const int krow = lane >> 4;        // k index of this lane in an MFMA operand
+  const int ntiles = (a.B + kScanN - 1) / kScanN;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int p_raw = tile * kScanN + n;
+    const bool valid = p_raw < a.B;
+    const int p = valid ? p_raw : a.B - 1;
+    const double* th = a.params + 5 * (int64_t)p;
+    const PeeCoef<R> k = pee_coef<R>(th);
+    const double norm = th[4];
+
+    // ---- 1. point pass ------------------------------------------------------
+    R mu0[PPT];
+    R J0[PPT][4];
+#pragma clang loop unroll(full)
+    for (int m = 0; m < PPT; ++m) {
+      const int j = bg + NG * m;
+      R mu = R(0);
+      R J[4] = {R(0), R(0), R(0), R(0)};
+      if (j < nb) {
+        for (int kk = 0; kk < a.ppb; ++kk) {
+          const int kq = j * a.ppb + kk;
+          const R fk = f_s[kq];
+          R pb = R(0);
+          R dpb[4] = {R(0), R(0), R(0), R(0)};
+          for (int r = 0; r < nL; ++r) {
+            R P, dP[4];
+            pee_point<R, GRAD>(k, q_s[r * nq + kq], P, dP);
+            const R wr = (R)w_s[r];
+            pb = rfma_t<R>(wr, P, pb);
+            if (GRAD) {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+            }
+          }
+          mu = rfma_t<R>(fk, pb, mu);
+          if (GRAD) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
+          }
+        }
+      }
+      mu0[m] = mu;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
+      if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
+    }
+    __syncthreads();
+
+    // ---- 2. nu = R mu ---------------------------------------------------------
+    A4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      acc[u] = A4{R(0), R(0), R(0), R(0)};
+      const int I = wave + u * NW;
+      if (I < mt) {
+        const int lo = a.kbA[2 * I], hi = a.kbA[2 * I + 1];
+        const R* At = a.RA + ((int64_t)I * mt) * 256 + lane;
+        for (int kb = lo; kb <= hi; ++kb) {
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const R av = At[(kb * 4 + st) * 64];
+            const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+            acc[u] = Acc<R>::mfma(av, bv, acc[u]);
+          }
+        }
+      }
+    }
+    __syncthreads();  // every wave is done reading mu
+
+    // ---- 3. chi2 and gnu --------------------------------------------------------
+    double chi = 0.0;
+    bool badnu = false;
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int I = wave + u * NW;
+      if (I < mt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = I * 16 + Acc<R>::row(krow, v);
+          if (i < nb) {
+            const double nu = (double)acc[u][v];
+            const double d = d_s[i];
+            if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
+            double term = nu - d;
+            if (d > 0.0) term += d * log(d / nu);
+            chi += term;
+            bb[i * kScanN + n] = (R)(2.0 * (1.0 - d / nu));
+            if (a.pred && valid) a.pred[(int64_t)p * nb + i] = nu;
+          } else {
+            bb[i * kScanN + n] = R(0);
+          }
+        }
+      }
+    }
+    if (badnu && valid)
+      __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    chi = xor_sum_16_32(chi);
+    if (lane < kScanN) red[(wave * kScanN + n) * 6] = chi;
+    __syncthreads();
+
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (GRAD) {
+      // ---- 4. gmu = R^T gnu ---------------------------------------------------
+      A4 acc2[TPW];
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        acc2[u] = A4{R(0), R(0), R(0), R(0)};
+        const int J = wave + u * NW;
+        if (J < mt) {
+          const int lo = a.kbT[2 * J], hi = a.kbT[2 * J + 1];
+          const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
+          for (int kb = lo; kb <= hi; ++kb) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+              const R av = At[(kb * 4 + st) * 64];
+              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+              acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+            }
+          }
+        }
+      }
+      __syncthreads();  // every wave is done reading gnu
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int J = wave + u * NW;
+        if (J < mt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bb[(J * 16 + Acc<R>::row(krow, v)) * kScanN + n] = acc2[u][v];
+        }
+      }
+      __syncthreads();
+
+      // ---- 5. gradient from the point-pass registers ------------------------------
+#pragma clang loop unroll(full)
+      for (int m = 0; m < PPT; ++m) {
+        const int j = bg + NG * m;
+        if (j < nb) {
+          const double gm = (double)bb[j * kScanN + n];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) g[c] += gm * (double)J0[m][c];
+          g[4] += gm * (double)mu0[m];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) g[c] = xor_sum_16_32(g[c]);
+      if (lane < kScanN) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) red[(wave * kScanN + n) * 6 + 1 + c] = g[c];
+      }
+      __syncthreads();
+    }
+
+    if (tid < kScanN && valid) {
+      double cs = 0.0, gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int w = 0; w < NW; ++w) {
+        cs += red[(w * kScanN + n) * 6];
+        if (GRAD) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) gs[c] += red[(w * kScanN + n) * 6 + 1 + c];
+        }
+      }
+      if (k.bad)
+        __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+      a.chi2[p] = k.bad ? NAN : 2.0 * cs;
+      if (GRAD && a.grad) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a.grad[5 * (int64_t)p + c] = k.bad ? NAN : norm * gs[c];
+        a.grad[5 * (int64_t)p + 4] = k.bad ? NAN : gs[4];
+      }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+// ---- configuration-stage tables -------------------------------------------
+__global__ void qtab_kernel(const double* __restrict__ E, const double* __restrict__ L, int nL,
+                            int nq, double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nL * nq) return;
+  const int r = (int)(i / nq), k = (int)(i - (int64_t)r * nq);
+  q[i] = (kPhase * L[r]) / E[k];
+}
+
+// A-operand tiles of R (transpose = 0) or R^T (transpose = 1):
+// tile (I, kb), step st, lane l holds M[I*16 + (l & 15)][kb*16 + 4 st + (l >> 4)].
+template <class R>
+__global__ void tile_kernel(const SliceDev* __restrict__ slices, const R* __restrict__ Rv, int nb,
+                            int mt, int transpose, R* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)mt * mt * 256) return;
+  const int l = (int)(idx & 63);
+  const int st = (int)((idx >> 6) & 3);
+  const int64_t t = idx >> 8;
+  const int kb = (int)(t % mt), I = (int)(t / mt);
+  const int a = I * 16 + (l & 15), b = kb * 16 + st * 4 + (l >> 4);
+  const int i = transpose ? b : a;  // row of R
+  const int j = transpose ? a : b;  // column of R
+  R v = R(0);
+  if (i < nb && j < nb) {
+    const SliceDev sd = slices[i / kSlice];
+    const int d = j - i;
+    if (d >= sd.dlo && d < sd.dlo + sd.nd) v = Rv[sd.off + (int64_t)(d - sd.dlo) * kSlice + (i % kSlice)];
+  }
+  out[idx] = v;
+}
+
+struct ScanLayout {
+  size_t RA, RT, kbA, kbT, qtab, total;
+};
+
+ScanLayout scan_layout(const gna_plan* p) {
+  ScanLayout L{};
+  const ProbDev& pd = p->probs[0];
+  const int mt = (pd.n_bins + 15) / 16;
+  const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
+  const int64_t nq = (int64_t)pd.n_bins * pd.ppb;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off = align_up(off + std::max<size_t>(b, 1), 256);
+    return at;
+  };
+  L.RA = take((size_t)mt * mt * 256 * rs);
+  L.RT = take((size_t)mt * mt * 256 * rs);
+  L.kbA = take((size_t)mt * 2 * 4);
+  L.kbT = take((size_t)mt * 2 * 4);
+  L.qtab = take((size_t)pd.n_L * nq * 8);
+  L.total = off;
+  return L;
+}
+
+int scan_threads(const gna_plan* p) {
+  const ProbDev& pd = p->probs[0];
+  const int mt = (pd.n_bins + 15) / 16;
+  const int nq = pd.n_bins * pd.ppb;
+  const bool fp64 = p->prec == GNA_FP64;
+  // 512 lanes: the gradient variant keeps mu0 / J0 of 8 bins in registers
+  // (~240 VGPRs in FP64) without spilling; 1024 lanes would cap it at 128.
+  for (int nt : {512}) {
+    const size_t b = fp64 ? scan_lds<double>(pd.n_L, nq, mt, nt / 64)
+                          : scan_lds<float>(pd.n_L, nq, mt, nt / 64);
+    if (b <= std::min(kScanLdsMax, p->lds_limit)) return nt;
+  }
   return 0;
 }
 
+template <class R, bool GRAD, int NT>
+int launch_scan_t(gna_plan* p, const ScanArgs<R>& a, hipStream_t s) {
+  const int nw = NT / 64;
+  const size_t lds = scan_lds<R>(a.nL, a.nq, a.mt, nw);
+  auto kern = scan_kernel<R, GRAD, NT>;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, lds) != hipSuccess || occ < 1)
+    occ = 1;
+  const int ntiles = (a.B + kScanN - 1) / kScanN;
+  const int grid = std::max(1, std::min(ntiles, occ * p->cu_count));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, a);
+  return check_hip(hipGetLastError(), "scan_kernel launch");
+}
+
+template <class R>
+int launch_scan_r(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
+                  double* pred, hipStream_t s) {
+  const ScanLayout SL = scan_layout(p);
+  const ProbDev& pd = p->probs[0];
+  unsigned char* w = p->ws;
+  unsigned char* base = w + p->lay.Rdense;
+  ScanArgs<R> a{};
+  a.B = B;
+  a.nb = pd.n_bins;
+  a.mt = (pd.n_bins + 15) / 16;
+  a.ppb = pd.ppb;
+  a.nL = pd.n_L;
+  a.nq = pd.n_bins * pd.ppb;
+  a.qtab = (const double*)(base + SL.qtab);
+  a.f = (const R*)(w + p->lay.f);
+  a.wL = (const double*)(w + p->lay.wL);
+  a.data = (const double*)(w + p->lay.data);
+  a.RA = (const R*)(base + SL.RA);
+  a.RT = (const R*)(base + SL.RT);
+  a.kbA = (const int32_t*)(base + SL.kbA);
+  a.kbT = (const int32_t*)(base + SL.kbT);
+  a.params = params;
+  a.chi2 = chi2;
+  a.grad = grad;
+  a.pred = pred;
+  a.status = (uint32_t*)(w + p->lay.status);
+  const int nt = scan_threads(p);
+  if (nt == 512)
+    return grad ? launch_scan_t<R, true, 512>(p, a, s) : launch_scan_t<R, false, 512>(p, a, s);
+  return fail(GNA_E_UNSUPPORTED, "scan kernel does not fit in LDS");
+}
+
+}  // namespace
+
+bool scan_supported(const gna_plan* p) {
+  if (p->kind != kChain || p->probs.empty()) return false;
+  const ProbDev& pd = p->probs[0];
+  if (pd.n_bins > kScanMaxBins) return false;
+  return scan_threads(p) != 0;
+}
+
+size_t scan_dense_bytes(const gna_plan* p) {
+  if (!scan_supported(p)) return 0;
+  return scan_layout(p).total;
+}
+
 int build_scan_tables(gna_plan* p, hipStream_t s) {
-  (void)p;
-  (void)s;
-  return GNA_OK;
+  const ScanLayout SL = scan_layout(p);
+  const ProbDev& pd = p->probs[0];
+  const int nb = pd.n_bins, mt = (nb + 15) / 16;
+  unsigned char* w = p->ws;
+  unsigned char* base = w + p->lay.Rdense;
+  // Block-band extents from the slices: row i holds columns
+  // [i + dlo, i + dlo + nd - 1] of its slice, clipped to the matrix.
+  std::vector<int32_t> kbA(2 * mt), kbT(2 * mt);
+  std::vector<int> colA_lo(mt, 1 << 30), colA_hi(mt, -1), rowT_lo(mt, 1 << 30), rowT_hi(mt, -1);
+  for (int i = 0; i < nb; ++i) {
+    const SliceDev& sd = p->slices[pd.slice_off + i / kSlice];
+    const int c0 = std::max(0, i + sd.dlo), c1 = std::min(nb - 1, i + sd.dlo + sd.nd - 1);
+    if (c1 < c0) continue;
+    const int I = i / 16;
+    colA_lo[I] = std::min(colA_lo[I], c0);
+    colA_hi[I] = std::max(colA_hi[I], c1);
+    for (int J = c0 / 16; J <= c1 / 16; ++J) {
+      rowT_lo[J] = std::min(rowT_lo[J], i);
+      rowT_hi[J] = std::max(rowT_hi[J], i);
+    }
+  }
+  for (int I = 0; I < mt; ++I) {
+    kbA[2 * I] = colA_hi[I] >= 0 ? colA_lo[I] / 16 : 0;
+    kbA[2 * I + 1] = colA_hi[I] >= 0 ? colA_hi[I] / 16 : -1;
+    kbT[2 * I] = rowT_hi[I] >= 0 ? rowT_lo[I] / 16 : 0;
+    kbT[2 * I + 1] = rowT_hi[I] >= 0 ? rowT_hi[I] / 16 : -1;
+  }
+  int rc = check_hip(hipMemcpyAsync(base + SL.kbA, kbA.data(), kbA.size() * 4,
+                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync (kbA)");
+  if (rc) return rc;
+  rc = check_hip(hipMemcpyAsync(base + SL.kbT, kbT.data(), kbT.size() * 4, hipMemcpyHostToDevice,
+                                s), "hipMemcpyAsync (kbT)");
+  if (rc) return rc;
+  const int64_t nq = (int64_t)nb * pd.ppb;
+  const int64_t nqt = nq * pd.n_L;
+  hipLaunchKernelGGL(qtab_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s,
+                     (const double*)(w + p->lay.E), (const double*)(w + p->lay.L), pd.n_L,
+                     (int)nq, (double*)(base + SL.qtab));
+  if ((rc = check_hip(hipGetLastError(), "qtab_kernel"))) return rc;
+  const int64_t nt = (int64_t)mt * mt * 256;
+  const unsigned g = (unsigned)((nt + 255) / 256);
+  const SliceDev* dsl = (const SliceDev*)(w + p->lay.slices) + pd.slice_off;
+  for (int tr = 0; tr < 2; ++tr) {
+    if (p->prec == GNA_FP64)
+      hipLaunchKernelGGL(tile_kernel<double>, dim3(g), dim3(256), 0, s, dsl,
+                         (const double*)(w + p->lay.Rv), nb, mt, tr,
+                         (double*)(base + (tr ? SL.RT : SL.RA)));
+    else
+      hipLaunchKernelGGL(tile_kernel<float>, dim3(g), dim3(256), 0, s, dsl,
+                         (const float*)(w + p->lay.Rv), nb, mt, tr,
+                         (float*)(base + (tr ? SL.RT : SL.RA)));
+    if ((rc = check_hip(hipGetLastError(), "tile_kernel"))) return rc;
+  }
+  // kbA / kbT host vectors die here.
+  return check_hip(hipStreamSynchronize(s), "hipStreamSynchronize (scan tables)");
 }
 
 int launch_scan(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
                 double* pred, hipStream_t s) {
-  (void)p;
-  (void)params;
-  (void)B;
-  (void)chi2;
-  (void)grad;
-  (void)pred;
-  (void)s;
-  return fail(GNA_E_UNSUPPORTED, "MFMA scan kernel not built");
+  if (!scan_supported(p)) return fail(GNA_E_UNSUPPORTED, "plan does not support the scan kernel");
+  if (p->prec == GNA_FP64) return launch_scan_r<double>(p, params, B, chi2, grad, pred, s);
+  return launch_scan_r<float>(p, params, B, chi2, grad, pred, s);
 }
 
 }  // namespace gna

@@ -1,0 +1,132 @@
+"""GPU parity of the batched scan kernel (MFMA smearing) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests.helpers import FP64_RTOL, grad_error, rel_err, with_data
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+MODEL = W.model()
+MIXED_PRED_RTOL = 2e-6
+MIXED_CHI2_RTOL = 1e-5
+MIXED_GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    return with_data(W.config0(), MODEL, W.SEED)
+
+
+def _plan(problem, B, prec="fp64", mfma=1):
+    import paper_1804_07682_amd as gna
+    return gna.Chain(problem, MODEL, max_batch=B, prec=prec, opts={"smear_mfma": mfma},
+                     device=DEV)
+
+
+def _eval(plan, P, pred=True, grad=True):
+    Pt = torch.tensor(np.atleast_2d(P), dtype=torch.float64, device=DEV)
+    out = plan.eval(Pt, grad=grad, pred=pred)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("B", [16, 37, 64])
+def test_scan_fp64_parity(cfg0, B):
+    P = W.config3_params(8, 8)[:B]
+    plan = _plan(cfg0, B)
+    assert plan.shape()["smear_mfma"] == 1
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+    assert plan.status() == 0
+
+
+def test_scan_mixed_error(cfg0):
+    P = W.config3_params(8, 8)
+    plan = _plan(cfg0, 64, prec="mixed")
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
+    e = (np.max(rel_err(got["pred"], ref["nu"])), np.max(rel_err(got["chi2"], ref["chi2"])),
+         np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])))
+    print(f"scan mixed: pred {e[0]:.2e} chi2 {e[1]:.2e} grad {e[2]:.2e}")
+    assert e[0] <= MIXED_PRED_RTOL and e[1] <= MIXED_CHI2_RTOL and e[2] <= MIXED_GRAD_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scan_matches_generic_kernel(cfg0, prec):
+    P = W.config3_params(4, 16)
+    a = _eval(_plan(cfg0, 64, prec=prec, mfma=1), P)
+    b = _eval(_plan(cfg0, 64, prec=prec, mfma=0), P)
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    assert np.max(rel_err(a["chi2"], b["chi2"])) <= tol * 10
+    assert np.max(rel_err(a["pred"], b["pred"])) <= tol
+    assert np.max(grad_error(a["grad"], b["grad"], P, b["chi2"])) <= tol * 100
+
+
+def test_scan_without_gradient(cfg0):
+    P = W.config3_params(2, 16)
+    plan = _plan(cfg0, 32)
+    a = _eval(plan, P, grad=False, pred=False)
+    b = _eval(plan, P)
+    assert np.array_equal(a["chi2"], b["chi2"])
+
+
+def test_scan_deterministic_and_batch_invariant(cfg0):
+    P = W.config3_params(4, 16)
+    plan = _plan(cfg0, 64)
+    a = _eval(plan, P)
+    b = _eval(plan, P)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+    # A point's result does not depend on its batch neighbours.
+    c = _eval(plan, P[[5, 0, 63]])
+    assert np.array_equal(c["chi2"], a["chi2"][[5, 0, 63]])
+
+
+def test_scan_domain_error(cfg0):
+    import paper_1804_07682_amd as gna
+    P = W.config3_params(1, 16)
+    P[3, 3] = -0.2
+    plan = _plan(cfg0, 16)
+    got = _eval(plan, P)
+    assert np.isnan(got["chi2"][3]) and np.all(np.isfinite(np.delete(got["chi2"], 3)))
+    with pytest.raises(gna.GnaError):
+        plan.status()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scan_full_size_sampled(cfg0, prec):
+    """The benchmark's 4096-point scan at its launch shape, 96 points vs the oracle."""
+    P = W.config3_params()
+    plan = _plan(cfg0, P.shape[0], prec=prec, mfma=-1)
+    assert plan.shape()["smear_mfma"] == 1
+    got = _eval(plan, P)
+    idx = np.random.default_rng(11).choice(P.shape[0], 96, replace=False)
+    idx[:2] = [0, P.shape[0] - 1]
+    ref = oracle.chain(cfg0, MODEL, P[idx], grad=True, nu=True, n_threads=8)
+    tol = (FP64_RTOL, FP64_RTOL, FP64_RTOL) if prec == "fp64" else \
+        (MIXED_PRED_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL)
+    assert np.max(rel_err(got["pred"][idx], ref["nu"])) <= tol[0]
+    assert np.max(rel_err(got["chi2"][idx], ref["chi2"])) <= tol[1]
+    assert np.max(grad_error(got["grad"][idx], ref["grad"], P[idx], ref["chi2"])) <= tol[2]
+    assert np.all(np.isfinite(got["chi2"]))
+
+
+def test_scan_odd_geometry(cfg0):
+    """Bins not a multiple of 16, several baselines, sub-intervals."""
+    pr = W.problem(W.uniform_edges(83), 4, [30.0, 52.5, 700.0], [0.2, 0.5, 0.3], n_sub=2)
+    pr = with_data(pr, MODEL, 5)
+    P = W.config3_params(3, 7)
+    plan = _plan(pr, 21)
+    assert plan.shape()["smear_mfma"] == 1
+    got = _eval(plan, P)
+    ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL

@@ -36,12 +36,13 @@ HBM_PEAK_GBPS = 8000.0
 # Vector ALU peak with unpacked FP32/FP64 FMAs: 256 CUs x 4 SIMDs x 16 lanes
 # x 2 flops x 2.4 GHz = 78.6 TFLOP/s (the kernels are built without packed FP32).
 ALU_PEAK_TFLOPS = 78.6
-# Algorithmic flops of one (point, baseline, parameter point) evaluation of P_ee
-# and its 4 tangents, with the FMA counted as 2 (see the roofline section of the
-# design notes): q = KL/E (2), 3 phases (3), per phase reduction + sin/cos
-# kernels + squares (43 x 3), P (6), tangents (18), baseline weight (10),
+# Flops of one (quadrature point, baseline, parameter point) evaluation of P_ee
+# and its 4 tangents in the scan kernel, FMA counted as 2 (q = KL/E is a
+# configuration-stage table there): 3 phases (3); per phase the reduction
+# (7), x (1), sin kernel (13), cos kernel (15), sin^2 / cos^2 / sin cos (3),
+# sin 2phi (1), i.e. 40 x 3; P (6); tangents (18); baseline weight (10);
 # flux factor (10).
-FLOPS_PER_PEE_GRAD_EVAL = 178
+FLOPS_PER_PEE_GRAD_EVAL = 167
 
 
 def log(msg):

@@ -43,34 +43,78 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Dynamic LDS of one work-group (sizes in chain_lds_bytes):
+//   stage [threads][5]        bin sums of a single-tile point
+//   mu    [max_bins]          norm * mu0
+//   gnu   [max_bins]          d chi2 / d nu
+//   part  [split][max_bins]   partial smearing sums of the diagonal chunks
+//   red   [waves][6]          per-wave chi2 and gradient partials
+//   flag
 struct TileLds {
   unsigned char* base;
   int threads;
   int max_bins;
-  template <class R>
-  __device__ R* stage() const {
-    return reinterpret_cast<R*>(base);
-  }
-  template <class R>
-  __device__ R* mu() const {
-    return reinterpret_cast<R*>(base + align16(threads * 5 * sizeof(R)));
-  }
-  template <class R>
-  __device__ R* gnu() const {
-    return reinterpret_cast<R*>(base + align16(threads * 5 * sizeof(R)) +
-                                align16(max_bins * sizeof(R)));
-  }
-  template <class R>
-  __device__ double* red() const {
-    return reinterpret_cast<double*>(base + align16(threads * 5 * sizeof(R)) +
-                                     2 * align16(max_bins * sizeof(R)));
-  }
-  template <class R>
-  __device__ int* flag() const {
-    return reinterpret_cast<int*>(red<R>() + (threads / kWave) * 6);
-  }
+  int split;
   __device__ static size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+  template <class R>
+  __device__ size_t o_mu() const { return align16((size_t)threads * 5 * sizeof(R)); }
+  template <class R>
+  __device__ size_t o_gnu() const { return o_mu<R>() + align16((size_t)max_bins * sizeof(R)); }
+  template <class R>
+  __device__ size_t o_part() const { return o_gnu<R>() + align16((size_t)max_bins * sizeof(R)); }
+  template <class R>
+  __device__ size_t o_red() const {
+    return o_part<R>() + align16((size_t)split * max_bins * sizeof(R));
+  }
+  template <class R>
+  __device__ R* stage() const { return reinterpret_cast<R*>(base); }
+  template <class R>
+  __device__ R* mu() const { return reinterpret_cast<R*>(base + o_mu<R>()); }
+  template <class R>
+  __device__ R* gnu() const { return reinterpret_cast<R*>(base + o_gnu<R>()); }
+  template <class R>
+  __device__ R* part() const { return reinterpret_cast<R*>(base + o_part<R>()); }
+  template <class R>
+  __device__ double* red() const { return reinterpret_cast<double*>(base + o_red<R>()); }
+  template <class R>
+  __device__ int* flag() const { return reinterpret_cast<int*>(red<R>() + (threads / kWave) * 6); }
 };
+
+// gmu_j = sum_i R_ij gnu_i over diagonals d in [d0, d1), for the 64 columns
+// j = 64 cb + lane.  Row i = j - d lies in slice cb - m (lanes >= r) or
+// cb - m - 1 (lanes < r), with d = 64 m + r: every lane is busy and each
+// slice is read as one contiguous segment.  Branch-free body (invalid lanes
+// read element 0 and add 0) so the unrolled loads issue back to back.
+template <class R>
+__device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict__ slices, int ns,
+                           int nb, const R* gnus, int cb, int lane, int d0, int d1) {
+  R acc = R(0);
+  int d = d0;
+  while (d < d1) {
+    const int m = d >> 6;  // floor(d / 64)
+    const int dend = min(d1, (m + 1) * kSlice);
+    const int sB = cb - m, sA = cb - m - 1;
+    const bool vB = sB >= 0 && sB < ns, vA = sA >= 0 && sA < ns;
+    const SliceDev zB = vB ? slices[sB] : SliceDev{0, 0, 0};
+    const SliceDev zA = vA ? slices[sA] : SliceDev{0, 0, 0};
+#pragma unroll 4
+    for (; d < dend; ++d) {
+      const int r = d - m * kSlice;
+      const bool useB = lane >= r;
+      const int s = useB ? sB : sA;
+      const int dlo = useB ? zB.dlo : zA.dlo;
+      const int nd = useB ? zB.nd : zA.nd;
+      const int64_t off = useB ? zB.off : zA.off;
+      const int li = useB ? lane - r : lane + kSlice - r;
+      const int i = s * kSlice + li;
+      const bool ok = (d >= dlo) && (d < dlo + nd) && (i < nb);
+      const R rv = Rv[ok ? off + (int64_t)(d - dlo) * kSlice + li : 0];
+      const R g = gnus[ok ? i : 0];
+      acc = rfma<R>(ok ? rv : R(0), g, acc);
+    }
+  }
+  return acc;
+}
 
 template <class R, bool GRAD>
 __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L) {
@@ -193,32 +237,46 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
 
   const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
   const int nwaves = NT / kWave;
+  const int ns = pd.n_slices;
   const SliceDev* slices = a.slices + pd.slice_off;
   const double* dat = a.data + pd.bin_off;
   double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)td.point * nb)
                         : nullptr;
-  double chi = 0.0;
-  bool badnu = false;
-  for (int s = wave; s < pd.n_slices; s += nwaves) {
+  R* part = L.part<R>();
+  const int maxb = L.max_bins;
+
+  // Forward smearing: work items (slice, chunk of its diagonals) over all waves.
+  const int Kf = min(L.split, max(1, nwaves / ns));
+  for (int item = wave; item < ns * Kf; item += nwaves) {
+    const int s = item / Kf, kap = item - (item / Kf) * Kf;
     const SliceDev sd = slices[s];
+    const int csz = (sd.nd + Kf - 1) / Kf;
+    const int d0 = kap * csz, d1 = min(sd.nd, d0 + csz);
     const int i = s * kSlice + lane;
     const R* rv = a.Rv + sd.off + lane;
     R acc = R(0);
-    for (int dd = 0; dd < sd.nd; ++dd) {
+#pragma unroll 8
+    for (int dd = d0; dd < d1; ++dd) {
       const int jj = i + sd.dlo + dd;
-      const R m = ((unsigned)jj < (unsigned)nb) ? mus[jj] : R(0);
-      acc = rfma<R>(rv[(int64_t)dd * kSlice], m, acc);
+      const R m = mus[((unsigned)jj < (unsigned)nb) ? jj : 0];
+      acc = rfma<R>(rv[(int64_t)dd * kSlice], ((unsigned)jj < (unsigned)nb) ? m : R(0), acc);
     }
-    if (i < nb) {
-      const double nu = (double)acc;
-      const double d = dat[i];
-      if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-      double term = nu - d;
-      if (d > 0.0) term += d * log(d / nu);
-      chi += term;
-      gnus[i] = (R)(2.0 * (1.0 - d / nu));
-      if (pred) pred[i] = nu;
-    }
+    if (i < nb) part[kap * maxb + i] = acc;
+  }
+  __syncthreads();
+  double chi = 0.0;
+  bool badnu = false;
+  for (int i = tid; i < nb; i += NT) {
+    R acc = R(0);
+    for (int kap = 0; kap < Kf; ++kap) acc += part[kap * maxb + i];
+    const double nu = (double)acc;
+    const double d = dat[i];
+    if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
+    double term = nu - d;
+    if (d > 0.0) term += d * log(d / nu);
+    chi += term;
+    gnus[i] = (R)(2.0 * (1.0 - d / nu));
+    if (pred) pred[i] = nu;
   }
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -229,31 +287,39 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
 
   double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (GRAD) {
+    // Adjoint smearing: work items (column block, chunk of its diagonals).
     const int ncb = (nb + kSlice - 1) / kSlice;
-    for (int cb = wave; cb < ncb; cb += nwaves) {
-      const int jc = cb * kSlice + lane;
-      R acc = R(0);
-      for (int s = 0; s < pd.n_slices; ++s) {
+    const int Ka = min(L.split, max(1, nwaves / ncb));
+    for (int item = wave; item < ncb * Ka; item += nwaves) {
+      const int cb = item / Ka, kap = item - (item / Ka) * Ka;
+      int dmin = 1 << 30, dmax = -(1 << 30);
+      for (int s = 0; s < ns; ++s) {
         const SliceDev sd = slices[s];
-        const int col_lo = s * kSlice + sd.dlo;
-        const int col_hi = s * kSlice + (kSlice - 1) + sd.dlo + sd.nd - 1;
-        if (col_hi < cb * kSlice || col_lo > cb * kSlice + kSlice - 1) continue;
-        const int dbeg = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
-        const int dend = min(sd.dlo + sd.nd, kSlice * (cb - s) + kSlice);
-        for (int d = dbeg; d < dend; ++d) {
-          const int li = jc - d - s * kSlice;  // row inside slice s
-          if ((unsigned)li < (unsigned)kSlice) {
-            const int i = s * kSlice + li;
-            if (i < nb) acc = rfma<R>(a.Rv[sd.off + (int64_t)(d - sd.dlo) * kSlice + li], gnus[i], acc);
-          }
+        const int lo = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
+        const int hi = min(sd.dlo + sd.nd - 1, kSlice * (cb - s) + (kSlice - 1));
+        if (lo <= hi) {
+          dmin = min(dmin, lo);
+          dmax = max(dmax, hi);
         }
       }
-      if (jc < nb) {
-        const double gmu = (double)acc;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) gs[c] += gmu * (double)J0_of(jc, c);
-        gs[4] += gmu * (double)mu0_of(jc);
+      R acc = R(0);
+      if (dmin <= dmax) {
+        const int span = dmax - dmin + 1;
+        const int csz = (span + Ka - 1) / Ka;
+        const int d0 = dmin + kap * csz, d1 = min(dmax + 1, d0 + csz);
+        acc = adjoint_range<R>(a.Rv, slices, ns, nb, gnus, cb, lane, d0, d1);
       }
+      const int jc = cb * kSlice + lane;
+      if (jc < nb) part[kap * maxb + jc] = acc;
+    }
+    __syncthreads();
+    for (int jc = tid; jc < nb; jc += NT) {
+      R acc = R(0);
+      for (int kap = 0; kap < Ka; ++kap) acc += part[kap * maxb + jc];
+      const double gmu = (double)acc;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gs[c] += gmu * (double)J0_of(jc, c);
+      gs[4] += gmu * (double)mu0_of(jc);
     }
 #pragma unroll
     for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
@@ -286,9 +352,9 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
 }
 
 template <class R, bool GRAD, bool PERSIST>
-__global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins) {
+__global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins, int split) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  TileLds L{lds_raw, (int)blockDim.x, max_bins};
+  TileLds L{lds_raw, (int)blockDim.x, max_bins, split};
   if (!PERSIST) {
     process_tile<R, GRAD>(a, (int64_t)blockIdx.x, L);
     return;
@@ -333,7 +399,8 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   if (grid > 0x7fffffffLL / sh.threads)
     return fail(GNA_E_UNSUPPORTED, "%lld tiles exceed one launch; use the persistent shape",
                 (long long)grid);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lds, s, a, p->max_bins);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lds, s, a, p->max_bins,
+                     chain_split(p, sh));
   return check_hip(hipGetLastError(), "chain_kernel launch");
 }
 

@@ -145,6 +145,7 @@ int build_scan_tables(gna_plan* p, hipStream_t s);
 bool scan_supported(const gna_plan* p);
 size_t scan_dense_bytes(const gna_plan* p);
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
+int chain_split(const gna_plan* p, const Shape& sh);
 // Sets the per-problem tiling of `sh` (and, for a fitset, rebuilds and
 // uploads the tile list when the plan has a workspace).
 int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s);

@@ -280,11 +280,20 @@ int64_t build_slices(const double* e, int nb, double res_a, std::vector<SliceDev
 // ---------------------------------------------------------------------------
 // Launch shapes.
 // ---------------------------------------------------------------------------
+// Number of diagonal chunks the smearing of one slice may be split into
+// (each chunk's partial sums take max_bins values of LDS).
+int chain_split(const gna_plan* p, const Shape& sh) {
+  const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
+  const int by_lds = (int)std::max<size_t>(1, 24576 / ((size_t)p->max_bins * rs));
+  return std::max(1, std::min({8, sh.threads / kWave, by_lds}));
+}
+
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
   const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  size_t b = align_up((size_t)sh.threads * 5 * rs, 16);  // per-tile bin sums
-  b += align_up((size_t)p->max_bins * rs, 16);           // mu
-  b += align_up((size_t)p->max_bins * rs, 16);           // d chi2 / d nu
+  size_t b = align_up((size_t)sh.threads * 5 * rs, 16);                    // per-tile bin sums
+  b += align_up((size_t)p->max_bins * rs, 16);                             // mu
+  b += align_up((size_t)p->max_bins * rs, 16);                             // d chi2 / d nu
+  b += align_up((size_t)chain_split(p, sh) * p->max_bins * rs, 16);        // chunk partials
   b += align_up((size_t)(sh.threads / kWave) * 6 * 8, 16);
   b += 16;  // flags
   return b;
@@ -335,7 +344,7 @@ Shape auto_shape(const gna_plan* p) {
 
 std::vector<Shape> shape_candidates(const gna_plan* p) {
   std::vector<Shape> out;
-  const int threads[] = {64, 128, 256, 512};
+  const int threads[] = {64, 128, 256, 512, 1024};
   const int Gs[] = {1, 2, 4, 8, 16, 32, 64};
   const int Cs[] = {1, 2, 4, 8, 16, 32, 64};
   double ppb, nL;

@@ -22,8 +22,11 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,6 +52,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_hash():
+    """Hash of the kernel sources: counter readings are valid only for this build."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1804_07682_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of `kernel_key` from profiles/traffic_pmc.txt (rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs, scaled by the same counters on the streaming
+    copy of known size), or None if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash\s+(\w+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    for line in text.splitlines():
+        if line.startswith("kernel ") and f"key={kernel_key} " in line + " ":
+            t = re.search(r"traffic_bytes=([0-9.eE+]+)", line)
+            return float(t.group(1)) if t else None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +86,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", default=None,
-                    help="run one workload for profiling: scan|scan64|pee|pee64|chain1|chain8|fitset")
+                    help="run one workload for profiling: scan|scan64|pee|pee64|copy|chain1|chain8|fitset")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the automatic launch shape (no autotuning), for counter runs")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     return ap.parse_args()
 
@@ -85,6 +117,9 @@ class Timer:
         return wall, float(k.mean()), float(np.median(k))
 
 
+TUNE = True
+
+
 def scan_setup(gna, W, torch, prec, dev):
     model = W.model()
     pr = W.config0()
@@ -95,6 +130,8 @@ def scan_setup(gna, W, torch, prec, dev):
     pr["data"] = W.poisson_counts(nu, W.SEED)
     P = torch.tensor(W.config3_params(), dtype=torch.float64, device=dev)
     plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev)
+    if TUNE:
+        plan.autotune(P, reps=10)
     return pr, model, plan, P
 
 
@@ -123,11 +160,12 @@ def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
     return res
 
 
-def copy_probe(torch, timer, dev, n=10 ** 8):
+def copy_probe(gna, torch, timer, dev, n=10 ** 8, steps=20):
+    """The library's streaming copy (16 B loads and stores, the P_ee grid shape)."""
     a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
     b = torch.empty_like(a)
-    wall, kmean, _ = timer.run(lambda: b.copy_(a), 10, 3)
-    return {"GBps": 16 * n / kmean / 1e9, "bytes": 16 * n}
+    wall, kmean, _ = timer.run(lambda: gna.gna_stream_copy(a, b), steps, 3)
+    return {"GBps": 16 * n / kmean / 1e9, "bytes": 16 * n, "kernel_ms": kmean * 1e3}
 
 
 def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec):
@@ -211,6 +249,8 @@ def cpu_baseline(W, pr_gpu):
 
 def main():
     args = parse()
+    global TUNE
+    TUNE = not args.no_tune
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the design notes describe how the scan would shard).", file=sys.stderr)
@@ -235,7 +275,8 @@ def main():
             r = bench_pee(gna, W, torch, timer, dev, 10 ** 8, 52.5,
                           "fp64" if o == "pee64" else "mixed", args.steps)
             log(f"{o}: {r}")
-            log(f"copy probe: {copy_probe(torch, timer, dev)}")
+        elif o == "copy":
+            log(f"copy probe: {copy_probe(gna, torch, timer, dev, steps=args.steps)}")
         elif o == "chain1":
             log(str(bench_chain_single(gna, W, torch, timer, dev, W.config0, W.SEED, args.steps,
                                        args.prec)))
@@ -274,7 +315,8 @@ def main():
         "pee_evals_per_s_per_chi2_eval": 1200,
         "roofline": {"bound": "alu", "kernel": "fused chain kernel (scan)",
                      "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic(f"scan_kernel<float,true,512,{main_r['shape']['smear_mfma'] + 1}>"),
                      "kernel_us": main_r["kernel_s"] * 1e6,
                      "flops_per_unit": FLOPS_PER_PEE_GRAD_EVAL, "units_per_launch": units},
     }
@@ -290,7 +332,10 @@ def main():
         pee = {}
         for prec in ("fp64", "mixed"):
             pee[prec] = bench_pee(gna, W, torch, timer, dev, 10 ** 8, 52.5, prec, 20)
-        pee["copy_probe"] = copy_probe(torch, timer, dev)
+        pee["copy_probe"] = copy_probe(gna, torch, timer, dev)
+        for prec, key in (("fp64", "pee_kernel<double,true>"), ("mixed", "pee_kernel<float,true>")):
+            pee[prec]["copy_frac"] = pee[prec]["GBps"] / pee["copy_probe"]["GBps"]
+            pee[prec]["traffic"] = measured_traffic(key)
         pee["workload"] = "N=1e8 energies uniform in [1.8, 12] MeV, L=52.5 km, one parameter point"
         line["pee"] = pee
         log("single-point chains ...")

@@ -93,6 +93,15 @@ int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double* L_km_host
             const double* wL_host, const double* theta_host, void* P_dev, int32_t prec,
             void* stream);
 
+/*
+ * Streaming copy dst_dev[i] = src_dev[i], i < n, with the elementwise
+ * kernel's access pattern and grid: the measured HBM-bandwidth reference of
+ * the benchmark and the known-size calibration of the memory-traffic
+ * counters (not a step of the chain).  Both pointers 16-byte aligned, not
+ * overlapping.  Asynchronous.  Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_stream_copy(const double* src_dev, double* dst_dev, int64_t n, void* stream);
+
 /* ---- chain description --------------------------------------------------- */
 /*
  * Model constants shared by all problems of a plan (readings of quantities the
@@ -149,9 +158,10 @@ typedef struct gna_problem {
  *                  on scheduling): 1..1024
  *   persistent     0: one work-group per tile; 1: a grid of
  *                  (CUs x occupancy) work-groups pulling tiles from a queue
- *   smear_mfma     (chain plans only) 1: batched kernel with the smearing as
- *                  a block-banded MFMA GEMM (needs n_bins <= 256);
- *                  0: banded smearing on the vector units; -1: automatic
+ *   smear_mfma     (chain plans only) 1, 2, 3: batched kernel with the
+ *                  smearing as a block-banded MFMA GEMM (needs n_bins <=
+ *                  256), register allocation for 2, 3 or 4 wavefronts per
+ *                  SIMD; 0: banded smearing on the vector units; -1: automatic
  */
 typedef struct gna_launch_opts {
   int32_t threads;

@@ -123,6 +123,17 @@ def gna_pee(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Tensor |
     return out
 
 
+def gna_stream_copy(src: torch.Tensor, dst: torch.Tensor):
+    """dst <- src with the elementwise kernel's access pattern (bandwidth reference)."""
+    _need_cuda(src, "src")
+    _need_cuda(dst, "dst")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst sizes differ")
+    check(load().gna_stream_copy(_ptr(src), _ptr(dst), src.numel(), _stream(src.device)),
+          "gna_stream_copy")
+    return dst
+
+
 def gna_gl_nodes(order: int, device="cuda"):
     t = torch.empty(order, dtype=torch.float64, device=device)
     w = torch.empty(order, dtype=torch.float64, device=device)

@@ -48,6 +48,10 @@ __device__ __forceinline__ T wave_sum(T v) {
 //   mu    [max_bins]          norm * mu0
 //   gnu   [max_bins]          d chi2 / d nu
 //   part  [split][max_bins]   partial smearing sums of the diagonal chunks
+//                             (absent when split == 1: the forward partials
+//                             then live in gnu, read and overwritten element
+//                             by element, and the adjoint partials in mu,
+//                             which the adjoint no longer reads)
 //   red   [waves][6]          per-wave chi2 and gradient partials
 //   flag
 struct TileLds {
@@ -64,7 +68,7 @@ struct TileLds {
   __device__ size_t o_part() const { return o_gnu<R>() + align16((size_t)max_bins * sizeof(R)); }
   template <class R>
   __device__ size_t o_red() const {
-    return o_part<R>() + align16((size_t)split * max_bins * sizeof(R));
+    return o_part<R>() + (split > 1 ? align16((size_t)split * max_bins * sizeof(R)) : 0);
   }
   template <class R>
   __device__ R* stage() const { return reinterpret_cast<R*>(base); }
@@ -73,7 +77,13 @@ struct TileLds {
   template <class R>
   __device__ R* gnu() const { return reinterpret_cast<R*>(base + o_gnu<R>()); }
   template <class R>
-  __device__ R* part() const { return reinterpret_cast<R*>(base + o_part<R>()); }
+  __device__ R* part_fwd() const {
+    return split > 1 ? reinterpret_cast<R*>(base + o_part<R>()) : gnu<R>();
+  }
+  template <class R>
+  __device__ R* part_adj() const {
+    return split > 1 ? reinterpret_cast<R*>(base + o_part<R>()) : mu<R>();
+  }
   template <class R>
   __device__ double* red() const { return reinterpret_cast<double*>(base + o_red<R>()); }
   template <class R>
@@ -151,7 +161,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
       R pb = R(0);
       R dpb[4] = {R(0), R(0), R(0), R(0)};
       for (int r = 0; r < pd.n_L; ++r) {
-        const double q = (kPhase * a.L[pd.L_off + r]) / E;
+        const double q = phase_per_ev2(kPhase * a.L[pd.L_off + r], E);
         const R wr = (R)a.wL[pd.L_off + r];
         R P, dP[4];
         pee_point<R, GRAD>(k, q, P, dP);
@@ -242,7 +252,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
   const double* dat = a.data + pd.bin_off;
   double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)td.point * nb)
                         : nullptr;
-  R* part = L.part<R>();
+  R* part = L.part_fwd<R>();
   const int maxb = L.max_bins;
 
   // Forward smearing: work items (slice, chunk of its diagonals) over all waves.
@@ -287,6 +297,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
 
   double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (GRAD) {
+    part = L.part_adj<R>();
     // Adjoint smearing: work items (column block, chunk of its diagonals).
     const int ncb = (nb + kSlice - 1) / kSlice;
     const int Ka = min(L.split, max(1, nwaves / ncb));

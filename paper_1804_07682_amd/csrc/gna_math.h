@@ -35,17 +35,32 @@ __device__ __forceinline__ double reduce_pio2(double phi, bool& odd) {
   return r;
 }
 
-// q = KL / E, correctly rounded (the IEEE division): FP64 phases are then
-// bit-identical to any other correctly rounded evaluation of (K L) / E.
-__device__ __forceinline__ double phase_per_ev2(double KL, double E) { return KL / E; }
+// Reciprocal of E > 0 to ~1 ulp.  The seed rsq(E)^2 is NaN for E < 0 and
+// inf for E = 0 (which the first Newton step turns into NaN), so a
+// non-positive energy yields NaN without a separate test; two Newton steps
+// take the ~2^-25 seed to full precision.
+__device__ __forceinline__ double recip_pos(double E) {
+  double y = __builtin_amdgcn_rsq(E);
+  y = y * y;
+  y = dfma(y, dfma(-E, y, 1.0), y);
+  y = dfma(y, dfma(-E, y, 1.0), y);
+  return y;
+}
 
-// q = KL / E within ~2 ulp: hardware reciprocal refined by two Newton steps
-// (mixed precision, where the phase needs ~1e-13 relative, not bit identity).
+// q = KL / E rounded to nearest: quotient from the reciprocal, then one
+// Markstein correction with the exactly computed remainder KL - E q.  For
+// normal-range operands (energies and baselines here) this is the correctly
+// rounded quotient, so FP64 phases match (K L) / E evaluated by an IEEE
+// division; non-positive E gives NaN.
+__device__ __forceinline__ double phase_per_ev2(double KL, double E) {
+  const double y = recip_pos(E);
+  const double q = KL * y;
+  return dfma(dfma(-E, q, KL), y, q);
+}
+
+// q = KL / E within ~2 ulp (mixed precision: the phase needs ~1e-13 relative).
 __device__ __forceinline__ double phase_per_ev2_fast(double KL, double E) {
-  double y = __builtin_amdgcn_rcp(E);
-  y = dfma(y, dfma(-E, y, 1.0), y);
-  y = dfma(y, dfma(-E, y, 1.0), y);
-  return KL * y;
+  return KL * recip_pos(E);
 }
 
 // sin r, cos r on |r| <= pi/4 (minimax kernels from trig_coeffs.h).
@@ -186,21 +201,34 @@ __device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
 }
 
 // P_ee and its four parameter derivatives at phase-per-eV^2 q = (K L) / E.
+// Each phase's terms are folded into P and the tangents as soon as they are
+// computed, which keeps few values live at once.
 template <class R, bool GRAD>
 __device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R dP[4]) {
+  const R qr = to_r<R>(q);
   const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
-  const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
-  const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
   R p = rfma_t<R>(k.A, t21.C, k.K0);
-  p = rfma_t<R>(k.B1, t31.C, p);
-  p = rfma_t<R>(k.B2, t32.C, p);
-  P = p;
+  R d0 = R(0), d1 = R(0), d2 = R(0), d3 = R(0);
   if (GRAD) {
-    const R qr = to_r<R>(q);
-    dP[0] = qr * (k.B2 * t32.T - k.A * t21.T);
-    dP[1] = -qr * (k.B1 * t31.T + k.B2 * t32.T);
-    dP[2] = -(k.dA12 * t21.S) - k.B * (t32.S - t31.S);
-    dP[3] = -(k.dA13 * t21.S) - k.dB13 * (k.c12 * t31.S + k.s12 * t32.S);
+    d0 = -(k.A * t21.T);
+    d2 = -(k.dA12 * t21.S);
+    d3 = -(k.dA13 * t21.S);
+  }
+  const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
+  p = rfma_t<R>(k.B1, t31.C, p);
+  if (GRAD) {
+    d1 = -(k.B1 * t31.T);
+    d2 = rfma_t<R>(k.B, t31.S, d2);
+    d3 = d3 - k.dB13 * (k.c12 * t31.S);
+  }
+  const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
+  P = rfma_t<R>(k.B2, t32.C, p);
+  if (GRAD) {
+    const R bt = k.B2 * t32.T;
+    dP[0] = qr * (d0 + bt);
+    dP[1] = qr * (d1 - bt);
+    dP[2] = d2 - k.B * t32.S;
+    dP[3] = d3 - k.dB13 * (k.s12 * t32.S);
   }
 }
 

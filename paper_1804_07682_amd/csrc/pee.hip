@@ -5,8 +5,9 @@
 // and 16-byte (FP64) or 8-byte (mixed) stores; the probability needs only
 // cos^2 of each phase, so one sin^2 polynomial per phase is evaluated
 // (cos^2 = 1 - sin^2 >= 1/2 on the reduced argument).  Phases and their
-// reduction are FP64 in both modes; FP64 mode divides q = KL / E exactly
-// (IEEE), mixed mode uses a refined reciprocal.
+// reduction are FP64 in both modes; q = KL / E comes from a refined
+// reciprocal (correctly rounded in FP64 mode, ~2 ulp in mixed mode).
+#include <algorithm>
 #include <cmath>
 
 #include "gna_internal.h"
@@ -40,7 +41,7 @@ __device__ __forceinline__ R pee_eval(const PeeArgs<R>& a, double E) {
     p = rfma_t<R>(a.B2, c32, p);
     acc = ONE_L ? p : acc + a.w[r] * p;
   }
-  return E > 0.0 ? acc : R(NAN);
+  return acc;  // NaN for E <= 0 (see recip_pos)
 }
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -124,7 +125,9 @@ int run_pee(const double* E, int64_t n, int32_t n_L, const double* L, const doub
   }
   const int64_t npairs = n >> 1;
   const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
-  const int64_t cap = (int64_t)cu_count() * 16;  // 16 resident groups of 4 waves per CU
+  // 256 groups per CU: a few pairs per lane and enough groups in flight to
+  // keep HBM busy (a smaller grid left the stream loop latency-bound).
+  const int64_t cap = (int64_t)cu_count() * 256;
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
   const bool oneL = (n_L == 1 && (!wL || wL[0] == 1.0));
   if (oneL)
@@ -168,4 +171,49 @@ extern "C" int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double
   if (prec == GNA_FP64)
     return run_pee<double>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
   return run_pee<float>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy (the measured-bandwidth reference for the elementwise kernel
+// and the known-size calibration of the memory-traffic counters): 16-byte
+// non-temporal loads and stores, the same grid shape as the P_ee kernel.
+// ---------------------------------------------------------------------------
+namespace gna {
+namespace {
+
+__global__ void __launch_bounds__(kPeeThreads)
+    copy_kernel(const double* __restrict__ src, int64_t n, double* __restrict__ dst) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const int64_t npairs = n >> 1;
+  const int64_t stride = (int64_t)gridDim.x * kPeeThreads;
+  const v2* s2 = reinterpret_cast<const v2*>(src);
+  v2* d2 = reinterpret_cast<v2*>(dst);
+  int64_t p = (int64_t)blockIdx.x * kPeeThreads + threadIdx.x;
+  for (; p + stride < npairs; p += 2 * stride) {
+    const v2 a = __builtin_nontemporal_load(s2 + p);
+    const v2 b = __builtin_nontemporal_load(s2 + p + stride);
+    __builtin_nontemporal_store(a, d2 + p);
+    __builtin_nontemporal_store(b, d2 + p + stride);
+  }
+  if (p < npairs) __builtin_nontemporal_store(__builtin_nontemporal_load(s2 + p), d2 + p);
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) dst[n - 1] = src[n - 1];
+}
+
+}  // namespace
+}  // namespace gna
+
+extern "C" int gna_stream_copy(const double* src_dev, double* dst_dev, int64_t n, void* stream) {
+  using namespace gna;
+  clear_error();
+  if (n < 0) return fail(GNA_E_INVAL, "gna_stream_copy: n < 0");
+  if (n == 0) return GNA_OK;
+  if (!src_dev || !dst_dev) return fail(GNA_E_INVAL, "gna_stream_copy: NULL pointer");
+  if (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15)
+    return fail(GNA_E_INVAL, "gna_stream_copy: pointers must be 16-byte aligned");
+  const int64_t npairs = n >> 1;
+  const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
+  const int blocks = (int)std::max<int64_t>(1, std::min(want, (int64_t)cu_count() * 256));
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(kPeeThreads), 0, (hipStream_t)stream, src_dev,
+                     n, dst_dev);
+  return check_hip(hipGetLastError(), "gna_stream_copy launch");
 }

@@ -280,23 +280,34 @@ int64_t build_slices(const double* e, int nb, double res_a, std::vector<SliceDev
 // ---------------------------------------------------------------------------
 // Launch shapes.
 // ---------------------------------------------------------------------------
-// Number of diagonal chunks the smearing of one slice may be split into
-// (each chunk's partial sums take max_bins values of LDS).
+// LDS of the generic kernel without the chunk partials.
+static size_t chain_lds_base(const gna_plan* p, const Shape& sh) {
+  const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
+  size_t b = align_up((size_t)sh.threads * 5 * rs, 16);  // per-tile bin sums
+  b += align_up((size_t)p->max_bins * rs, 16);           // mu
+  b += align_up((size_t)p->max_bins * rs, 16);           // d chi2 / d nu
+  b += align_up((size_t)(sh.threads / kWave) * 6 * 8, 16);
+  b += 16;  // flags
+  return b;
+}
+
+// Number of diagonal chunks the smearing of one slice may be split into: each
+// chunk's partial sums take max_bins values of LDS.  With one chunk no
+// partial buffer is needed (the kernel reuses the mu and gnu arrays).
 int chain_split(const gna_plan* p, const Shape& sh) {
   const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  const int by_lds = (int)std::max<size_t>(1, 24576 / ((size_t)p->max_bins * rs));
-  return std::max(1, std::min({8, sh.threads / kWave, by_lds}));
+  const size_t base = chain_lds_base(p, sh);
+  if (base >= p->lds_limit) return 1;
+  const size_t room = (p->lds_limit - base) / ((size_t)p->max_bins * rs);
+  const int split = (int)std::min<size_t>({8, (size_t)(sh.threads / kWave), room});
+  return split >= 2 ? split : 1;
 }
 
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
   const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  size_t b = align_up((size_t)sh.threads * 5 * rs, 16);                    // per-tile bin sums
-  b += align_up((size_t)p->max_bins * rs, 16);                             // mu
-  b += align_up((size_t)p->max_bins * rs, 16);                             // d chi2 / d nu
-  b += align_up((size_t)chain_split(p, sh) * p->max_bins * rs, 16);        // chunk partials
-  b += align_up((size_t)(sh.threads / kWave) * 6 * 8, 16);
-  b += 16;  // flags
-  return b;
+  const int split = chain_split(p, sh);
+  const size_t part = split > 1 ? align_up((size_t)split * p->max_bins * rs, 16) : 0;
+  return chain_lds_base(p, sh) + part;
 }
 
 namespace {
@@ -368,9 +379,11 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
       }
     }
   if (p->kind == kChain && scan_supported(p)) {
-    Shape sh;
-    sh.mfma = 1;
-    out.push_back(sh);
+    for (int v = 1; v <= 3; ++v) {
+      Shape sh;
+      sh.mfma = v;
+      out.push_back(sh);
+    }
   }
   return out;
 }
@@ -520,8 +533,8 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       return fail(GNA_E_INVAL, "opts.chunks = %d outside 0..1024", opts->chunks);
     if (opts->persistent < 0 || opts->persistent > 1)
       return fail(GNA_E_INVAL, "opts.persistent = %d not 0/1", opts->persistent);
-    if (opts->smear_mfma < -1 || opts->smear_mfma > 1)
-      return fail(GNA_E_INVAL, "opts.smear_mfma = %d not in -1..1", opts->smear_mfma);
+    if (opts->smear_mfma < -1 || opts->smear_mfma > 3)
+      return fail(GNA_E_INVAL, "opts.smear_mfma = %d not in -1..3", opts->smear_mfma);
   }
   for (int i = 0; i < n_probs; ++i) {
     rc = validate_problem(problems + i, i);
@@ -605,7 +618,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
     if (opts->lanes_per_bin) sh.G = std::min(opts->lanes_per_bin, sh.threads);
     if (opts->chunks) sh.C = opts->chunks;
     sh.persistent = opts->persistent;
-    if (opts->smear_mfma == 1) sh.mfma = 1;
+    if (opts->smear_mfma >= 1) sh.mfma = opts->smear_mfma;
   }
   if (kind == kChain && (!opts || opts->smear_mfma == -1) && scan_supported(p) &&
       n_points >= 64)

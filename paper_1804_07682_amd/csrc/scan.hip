@@ -89,8 +89,11 @@ __device__ __forceinline__ T xor_sum_16_32(T v) {
   return v;
 }
 
-template <class R, bool GRAD, int NT>
-__global__ void __launch_bounds__(NT) scan_kernel(ScanArgs<R> a) {
+// WPE: wavefronts per SIMD the register allocation must allow (2 = the
+// natural ~240-register allocation of the FP64 gradient variant; 3 and 4
+// trade spills of the per-bin sums for occupancy; the autotuner chooses).
+template <class R, bool GRAD, int NT, int WPE>
+__global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   using A4 = typename Acc<R>::T;
   constexpr int NW = NT / kWave;
   constexpr int NG = NT / kScanN;           // bin groups
@@ -370,11 +373,11 @@ int scan_threads(const gna_plan* p) {
   return 0;
 }
 
-template <class R, bool GRAD, int NT>
+template <class R, bool GRAD, int NT, int WPE>
 int launch_scan_t(gna_plan* p, const ScanArgs<R>& a, hipStream_t s) {
   const int nw = NT / 64;
   const size_t lds = scan_lds<R>(a.nL, a.nq, a.mt, nw);
-  auto kern = scan_kernel<R, GRAD, NT>;
+  auto kern = scan_kernel<R, GRAD, NT, WPE>;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, lds) != hipSuccess || occ < 1)
     occ = 1;
@@ -412,9 +415,15 @@ int launch_scan_r(gna_plan* p, const double* params, int32_t B, double* chi2, do
   a.pred = pred;
   a.status = (uint32_t*)(w + p->lay.status);
   const int nt = scan_threads(p);
-  if (nt == 512)
-    return grad ? launch_scan_t<R, true, 512>(p, a, s) : launch_scan_t<R, false, 512>(p, a, s);
-  return fail(GNA_E_UNSUPPORTED, "scan kernel does not fit in LDS");
+  if (nt != 512) return fail(GNA_E_UNSUPPORTED, "scan kernel does not fit in LDS");
+  switch (p->shape.mfma) {
+    case 2:
+      return grad ? launch_scan_t<R, true, 512, 3>(p, a, s) : launch_scan_t<R, false, 512, 3>(p, a, s);
+    case 3:
+      return grad ? launch_scan_t<R, true, 512, 4>(p, a, s) : launch_scan_t<R, false, 512, 4>(p, a, s);
+    default:
+      return grad ? launch_scan_t<R, true, 512, 2>(p, a, s) : launch_scan_t<R, false, 512, 2>(p, a, s);
+  }
 }
 
 }  // namespace

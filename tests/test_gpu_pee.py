@@ -100,3 +100,13 @@ def test_pee_full_size_sampled():
         assert np.max(rel_err(got[idx], ref)) <= FP64_RTOL
         gotm = _run(E, L, prec="mixed")
         assert np.max(np.abs(gotm[idx] - ref)) <= MIXED_ATOL
+
+
+def test_stream_copy():
+    import paper_1804_07682_amd as gna
+    for n in (0, 1, 2, 7, 1_000_001):
+        a = torch.from_numpy(W.config1_energies(max(n, 1))[:n]).to(DEV)
+        b = torch.full_like(a, -1.0)
+        gna.gna_stream_copy(a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)

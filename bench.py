@@ -206,6 +206,49 @@ def bench_fitset(gna, W, torch, timer, dev, steps, prec):
             "shape": plan.shape()}
 
 
+def table1_gpu(gna, W, torch, timer, dev):
+    """GPU side of the Table-1 analogue (FP64 P_ee, 52.5 km): compute-only
+    kernel time, and time with the host transfers of E (H2D) and P (D2H)
+    through pinned buffers, per evaluation."""
+    out = {}
+    for n in (10 ** 4, 10 ** 6):
+        E_host = torch.from_numpy(W.config1_energies(n)).pin_memory()
+        P_host = torch.empty(n, dtype=torch.float64).pin_memory()
+        E_dev = E_host.to(dev)
+        P_dev = torch.empty(n, dtype=torch.float64, device=dev)
+        _, kmean, _ = timer.run(lambda: gna.gna_pee(E_dev, 52.5, W.THETA0, out=P_dev), 200, 10)
+
+        def with_transfers():
+            E_dev.copy_(E_host, non_blocking=True)
+            gna.gna_pee(E_dev, 52.5, W.THETA0, out=P_dev)
+            P_host.copy_(P_dev, non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+
+        for _ in range(10):
+            with_transfers()
+        reps = 200
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            with_transfers()
+        out[str(n)] = {"gpu_compute_s": kmean, "gpu_with_transfers_s": (time.perf_counter() - t0) / reps}
+    return out
+
+
+def table1_cpu(W, threads):
+    import oracle
+    res = {}
+    for n in (10 ** 4, 10 ** 6):
+        E = W.config1_energies(n)
+        for nt, tag in ((1, "cpu_1core_s"), (threads, "cpu_all_cores_s")):
+            oracle.pee(E, 52.5, W.THETA0, n_threads=nt)
+            reps = max(1, int(2e6 // n))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                oracle.pee(E, 52.5, W.THETA0, n_threads=nt)
+            res.setdefault(str(n), {})[tag] = (time.perf_counter() - t0) / reps
+    return res
+
+
 def mixed_errors(gna, W, torch, dev, pr, P):
     model = W.model()
     res = {}
@@ -223,6 +266,11 @@ def mixed_errors(gna, W, torch, dev, pr, P):
     return res
 
 
+def cpu_threads():
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return max(1, min(threads, os.cpu_count() or 1))
+
+
 def cpu_baseline(W, pr_gpu):
     """The oracle, as it stands, on the scan workload (its own pseudo-data)."""
     import oracle
@@ -230,8 +278,7 @@ def cpu_baseline(W, pr_gpu):
     pr = W.config0()
     pr["data"] = W.poisson_counts(oracle.prediction(pr, model, W.THETA0), W.SEED)
     P = W.config3_params()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = max(1, min(threads, os.cpu_count() or 1))
+    threads = cpu_threads()
     oracle.chain(pr, model, P[:64], grad=True, n_threads=threads)  # warm-up
     t0 = time.perf_counter()
     reps = 0
@@ -346,8 +393,20 @@ def main():
         log("fitset ...")
         line["fitset"] = {p: bench_fitset(gna, W, torch, timer, dev, 10, p)
                           for p in ("fp64", "mixed")}
+        log("table-1 analogue (GPU side) ...")
+        t1_gpu = table1_gpu(gna, W, torch, timer, dev)
     log("cpu baseline (oracle) ...")
     line["cpu_baseline"] = cpu_baseline(W, main_r["pr"])
+    if not args.quick:
+        # Context only: the paper's Table 1 ratios (FP64 OscProb, i7-6700HQ vs GTX
+        # 970M) were 0.017 / 1.39 with transfers and 20.90 / 26.46 compute-only.
+        t1 = table1_cpu(W, cpu_threads())
+        for n, g in t1_gpu.items():
+            t1[n].update(g)
+            for tag in ("cpu_1core_s", "cpu_all_cores_s"):
+                t1[n][f"ratio_{tag[:-2]}_over_gpu_with_transfers"] = t1[n][tag] / g["gpu_with_transfers_s"]
+                t1[n][f"ratio_{tag[:-2]}_over_gpu_compute"] = t1[n][tag] / g["gpu_compute_s"]
+        line["cpu_baseline"]["table1_analogue"] = t1
     print(json.dumps(line, default=lambda o: o if not isinstance(o, np.generic) else o.item()),
           flush=True)
 

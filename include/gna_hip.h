@@ -94,6 +94,27 @@ int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double* L_km_host
             void* stream);
 
 /*
+ * General vacuum oscillation probability of Sec. 4.1 (its full equation):
+ *   P(a -> b) = delta_ab - 4 sum_{i>j} Re(X_ij) sin^2(dm2_ij L / 4E)
+ *                        + 2 sum_{i>j} Im(X_ij) sin(dm2_ij L / 2E),
+ *   X_ij = V*_ai V_bi V_aj V*_bj,
+ * V the PMNS matrix in the standard parametrisation by (theta12, theta13,
+ * theta23, delta_CP); for antineutrinos V -> V* (delta -> -delta).
+ * P_dev[i] = sum_r w_r P(E_dev[i]; L_r).
+ *   alpha, beta     flavours 0 = e, 1 = mu, 2 = tau
+ *   angles_host     host, 4 doubles: theta12, theta13, theta23, delta_CP [rad]
+ *   dm2_host        host, 2 doubles: dm2_21, dm2_31 [eV^2] (any signs)
+ *   antineutrino    0 or 1
+ *   E_dev, n, n_L, L_km_host, wL_host, P_dev, prec as for gna_pee (E_dev and
+ *   P_dev 8-byte aligned; P_dev holds floats in GNA_MIXED).
+ * Asynchronous.  Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_prob(const double* E_dev, int64_t n, int32_t alpha, int32_t beta, int32_t n_L,
+             const double* L_km_host, const double* wL_host, const double* angles_host,
+             const double* dm2_host, int32_t antineutrino, void* P_dev, int32_t prec,
+             void* stream);
+
+/*
  * Streaming copy dst_dev[i] = src_dev[i], i < n, with the elementwise
  * kernel's access pattern and grid: the measured HBM-bandwidth reference of
  * the benchmark and the known-size calibration of the memory-traffic

@@ -123,6 +123,33 @@ def gna_pee(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Tensor |
     return out
 
 
+FLAVOURS = {"e": 0, "mu": 1, "tau": 2, 0: 0, 1: 1, 2: 2}
+
+
+def gna_prob(E: torch.Tensor, alpha, beta, L, angles, dm2, wL=None, antineutrino=False,
+             prec="fp64", out: torch.Tensor | None = None):
+    """General P(nu_alpha -> nu_beta) of Sec. 4.1 over a resident energy vector.
+
+    alpha, beta: 'e' | 'mu' | 'tau' (or 0, 1, 2); angles = (th12, th13, th23,
+    delta_CP) in radians; dm2 = (dm2_21, dm2_31) in eV^2.
+    """
+    _need_cuda(E, "E")
+    pr = _prec(prec)
+    L = _f64(np.atleast_1d(L))
+    wLa = None if wL is None else _f64(wL)
+    ang = _f64(angles)[:4].copy()
+    dm = _f64(dm2)[:2].copy()
+    odt = torch.float64 if pr == GNA_FP64 else torch.float32
+    if out is None:
+        out = torch.empty(E.numel(), dtype=odt, device=E.device)
+    else:
+        _need_cuda(out, "out", odt)
+    check(load().gna_prob(_ptr(E), E.numel(), FLAVOURS[alpha], FLAVOURS[beta], L.size, _dptr(L),
+                          _dptr(wLa), _dptr(ang), _dptr(dm), int(bool(antineutrino)), _ptr(out),
+                          pr, _stream(E.device)), "gna_prob")
+    return out
+
+
 def gna_stream_copy(src: torch.Tensor, dst: torch.Tensor):
     """dst <- src with the elementwise kernel's access pattern (bandwidth reference)."""
     _need_cuda(src, "src")

@@ -97,8 +97,7 @@ __device__ __forceinline__ void sincos_kernel(float r, float& s, float& c) {
 // sin^2 r on |r| <= pi/4.
 __device__ __forceinline__ double sin2_kernel(double r) {
   const double x = r * r;
-  double p = GNA_QD7;
-  p = dfma(p, x, GNA_QD6);
+  double p = GNA_QD6;
   p = dfma(p, x, GNA_QD5);
   p = dfma(p, x, GNA_QD4);
   p = dfma(p, x, GNA_QD3);

@@ -5,10 +5,14 @@ Gauss-Legendre bin integration, smearing, Poisson chi^2 and its 5-component
 gradient -- for the batched scan: 4096 parameter points on a 64 x 64 grid in
 (dm2_31, sin^2 th13), 240 bins x 5 Gauss-Legendre nodes (1200 points), one
 52.5 km baseline, mixed precision.  `value` is chi^2+gradient evaluations per
-second (parameter points per second), inputs resident in HBM.
+second (parameter points per second), inputs resident in HBM.  Tiles of 16
+points with common (dm2_21, dm2_31) -- every tile of this grid, whose fast
+axis is sin^2 th13 -- evaluate their phases once (the library's default).
 
 The same JSON line also carries, measured in this run:
   * fp64: the same scan in plain FP64;
+  * per_point_phases: the same scan with phase sharing switched off (every
+    point evaluates its own phases), mixed and FP64;
   * pee: elementwise P_ee over N = 1e8 energies (52.5 km) in FP64 and mixed,
     evaluations/s and HBM bandwidth against 8 TB/s;
   * chain_1pt / chain_8L / fitset: the single-point chain (1200 points), the
@@ -46,6 +50,29 @@ ALU_PEAK_TFLOPS = 78.6
 # sin 2phi (1), i.e. 40 x 3; P (6); tangents (18); baseline weight (10);
 # flux factor (10).
 FLOPS_PER_PEE_GRAD_EVAL = 167
+# A tile of 16 points with common (dm2_21, dm2_31) shares its phases: per
+# (quadrature point, baseline) item the three phases' terms (3 x 40), the
+# weights f w and f w q (2) and 10 weighted sums (19); per (parameter point,
+# bin) mu in the point pass (7), and mu (7), the four tangents (17) and the
+# five gradient sums (10) in the gradient pass.
+FLOPS_SHARED_PER_ITEM = 141
+FLOPS_SHARED_PER_POINT_BIN = 41
+SCAN_TILE = 16
+
+
+def scan_flops(P, n_items, n_bins, share=True):
+    """Algorithmic flops of one scan launch: shared tiles pay the per-item sums
+    once plus the per-point combination; other tiles pay every evaluation."""
+    P = np.asarray(P)
+    flops = 0
+    for t in range(0, P.shape[0], SCAN_TILE):
+        blk = P[t:t + SCAN_TILE]
+        if share and np.all(blk[:, 0] == blk[0, 0]) and np.all(blk[:, 1] == blk[0, 1]):
+            flops += n_items * FLOPS_SHARED_PER_ITEM + \
+                blk.shape[0] * n_bins * FLOPS_SHARED_PER_POINT_BIN
+        else:
+            flops += blk.shape[0] * n_items * FLOPS_PER_PEE_GRAD_EVAL
+    return flops
 
 
 def log(msg):
@@ -86,7 +113,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", default=None,
-                    help="run one workload for profiling: scan|scan64|pee|pee64|copy|chain1|chain8|fitset")
+                    help="run one workload for profiling: scan|scan64|scan_pp|scan64_pp|pee|pee64|copy|"
+                         "chain1|chain8|fitset")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the automatic launch shape (no autotuning), for counter runs")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
@@ -120,7 +148,7 @@ class Timer:
 TUNE = True
 
 
-def scan_setup(gna, W, torch, prec, dev):
+def scan_setup(gna, W, torch, prec, dev, share=True):
     model = W.model()
     pr = W.config0()
     # Pseudo-data: Poisson counts drawn from this library's own FP64 prediction.
@@ -129,21 +157,24 @@ def scan_setup(gna, W, torch, prec, dev):
                   pred=True)["pred"].cpu().numpy()[0]
     pr["data"] = W.poisson_counts(nu, W.SEED)
     P = torch.tensor(W.config3_params(), dtype=torch.float64, device=dev)
-    plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev)
+    plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev,
+                     opts=None if share else {"no_shared_phases": 1})
     if TUNE:
         plan.autotune(P, reps=10)
     return pr, model, plan, P
 
 
-def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup):
-    pr, model, plan, P = scan_setup(gna, W, torch, prec, dev)
+def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup, share=True):
+    pr, model, plan, P = scan_setup(gna, W, torch, prec, dev, share)
     out = {"chi2": torch.empty(P.shape[0], dtype=torch.float64, device=dev),
            "grad": torch.empty((P.shape[0], 5), dtype=torch.float64, device=dev)}
     fn = lambda: plan.eval(P, grad=True, out=out)
     wall, kmean, kmed = timer.run(fn, steps, warmup)
     plan.status()
+    flops = scan_flops(P.cpu().numpy(), 1200, 240, share)
     return {"plan": plan, "pr": pr, "P": P, "wall": wall, "kernel_s": kmean, "kernel_med_s": kmed,
-            "evals_per_s": P.shape[0] * steps / wall, "shape": plan.shape()}
+            "evals_per_s": P.shape[0] * steps / wall, "shape": plan.shape(),
+            "flops": flops, "tflops": flops / kmean / 1e12}
 
 
 def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
@@ -313,9 +344,9 @@ def main():
 
     if args.only:
         o = args.only
-        if o in ("scan", "scan64"):
-            r = bench_scan(gna, W, torch, timer, "fp64" if o == "scan64" else "mixed", dev,
-                           args.steps, args.warmup)
+        if o in ("scan", "scan64", "scan_pp", "scan64_pp"):
+            r = bench_scan(gna, W, torch, timer, "fp64" if o.startswith("scan64") else "mixed",
+                           dev, args.steps, args.warmup, share=not o.endswith("_pp"))
             log(f"{o}: {r['evals_per_s']:.4g} evals/s kernel {r['kernel_s'] * 1e6:.1f} us "
                 f"shape {r['shape']}")
         elif o in ("pee", "pee64"):
@@ -338,8 +369,7 @@ def main():
     torch.cuda.synchronize()
     main_r = bench_scan(gna, W, torch, timer, "mixed", dev, args.steps, args.warmup)
     B = main_r["P"].shape[0]
-    units = B * 1200  # (point, baseline, parameter) evaluations per launch
-    achieved = FLOPS_PER_PEE_GRAD_EVAL * units / main_r["kernel_s"] / 1e12
+    achieved = main_r["tflops"]
     line = {
         "metric": "chi2+grad evals/s (batched scan, mixed precision; P_ee evals/s in pee)",
         "value": main_r["evals_per_s"],
@@ -363,9 +393,14 @@ def main():
         "roofline": {"bound": "alu", "kernel": "fused chain kernel (scan)",
                      "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic(f"scan_kernel<float,true,512,{main_r['shape']['smear_mfma'] + 1}>"),
+                     "traffic": measured_traffic(
+                         f"scan_kernel<float,true,512,{main_r['shape']['smear_mfma'] + 1},true>"),
                      "kernel_us": main_r["kernel_s"] * 1e6,
-                     "flops_per_unit": FLOPS_PER_PEE_GRAD_EVAL, "units_per_launch": units},
+                     "flops_per_launch": main_r["flops"],
+                     "flop_model": f"shared tiles: {FLOPS_SHARED_PER_ITEM} per (quadrature point, "
+                                   f"baseline) + {FLOPS_SHARED_PER_POINT_BIN} per (point, bin); "
+                                   f"other tiles: {FLOPS_PER_PEE_GRAD_EVAL} per (quadrature "
+                                   f"point, baseline, point)"},
     }
     if not args.quick:
         log("scan (fp64) ...")
@@ -373,6 +408,15 @@ def main():
         line["fp64"] = {"value": r64["evals_per_s"], "kernel_us": r64["kernel_s"] * 1e6,
                         "mixed_speedup": main_r["evals_per_s"] / r64["evals_per_s"],
                         "shape": r64["shape"]}
+        log("scan with per-point phases ...")
+        pp = {}
+        for prec in ("mixed", "fp64"):
+            r = bench_scan(gna, W, torch, timer, prec, dev, args.steps, args.warmup, share=False)
+            pp[prec] = {"value": r["evals_per_s"], "kernel_us": r["kernel_s"] * 1e6,
+                        "achieved_tflops": r["tflops"], "frac": r["tflops"] / ALU_PEAK_TFLOPS,
+                        "shape": r["shape"]}
+        pp["note"] = "every point evaluates its own phases (no_shared_phases=1)"
+        line["per_point_phases"] = pp
         log("mixed vs fp64 errors ...")
         line["mixed_vs_fp64"] = mixed_errors(gna, W, torch, dev, main_r["pr"], main_r["P"])
         log("pee N=1e8 ...")

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GNA_ABI_VERSION 1
+#define GNA_ABI_VERSION 2
 
 /* ---- status codes -------------------------------------------------------- */
 #define GNA_OK 0
@@ -183,6 +183,15 @@ typedef struct gna_problem {
  *                  smearing as a block-banded MFMA GEMM (needs n_bins <=
  *                  256), register allocation for 2, 3 or 4 wavefronts per
  *                  SIMD; 0: banded smearing on the vector units; -1: automatic
+ *   no_shared_phases  0 (default): in the batched MFMA kernel a tile of 16
+ *                  parameter points that all have the same (dm2_21, dm2_31)
+ *                  evaluates the phase terms once and sums them per bin
+ *                  before combining them with each point's mixing weights
+ *                  (a transformation is recomputed only when its own inputs
+ *                  change, Sec. 2); results agree with the per-point path to
+ *                  rounding, so a point's last bits may depend on its tile
+ *                  neighbours.  1: every point evaluates its own phases, and
+ *                  its result does not depend on the rest of the batch.
  */
 typedef struct gna_launch_opts {
   int32_t threads;
@@ -190,6 +199,7 @@ typedef struct gna_launch_opts {
   int32_t chunks;
   int32_t persistent;
   int32_t smear_mfma;
+  int32_t no_shared_phases;
 } gna_launch_opts;
 
 typedef struct gna_plan gna_plan;

@@ -96,6 +96,7 @@ def make_opts(opts) -> LaunchOpts | None:
     o.chunks = int(opts.get("chunks", 0))
     o.persistent = int(opts.get("persistent", 0))
     o.smear_mfma = int(opts.get("smear_mfma", -1))
+    o.no_shared_phases = int(bool(opts.get("no_shared_phases", 0)))
     return o
 
 

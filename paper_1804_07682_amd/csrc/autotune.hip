@@ -138,7 +138,7 @@ extern "C" int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32
   hipEvent_t e0, e1;
   if ((rc = check_hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
   if ((rc = check_hip(hipEventCreate(&e1), "hipEventCreate"))) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return rc;
   }
   double best_ms = 1e300;
@@ -163,8 +163,8 @@ extern "C" int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32
       best = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (best_ms >= 1e300) best = start;
   if ((rc = apply_shape(plan, best, s))) return rc;
   if (cache_path) cache_store(cache_path, key, best);

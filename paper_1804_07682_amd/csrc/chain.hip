@@ -396,16 +396,21 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bin
 template <class R, bool GRAD, bool PERSIST>
 int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   const Shape& sh = p->shape;
-  const size_t lds = chain_lds_bytes(p, sh);
   auto kern = chain_kernel<R, GRAD, PERSIST>;
-  int64_t grid = a.n_tiles;
-  if (PERSIST) {
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, sh.threads, lds) != hipSuccess ||
-        occ < 1)
-      occ = 1;
-    grid = std::min<int64_t>(a.n_tiles, (int64_t)occ * p->cu_count);
+  gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
+  if (!lc.ready) {
+    lc.lds = chain_lds_bytes(p, sh);
+    lc.occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&lc.occ, kern, sh.threads, lc.lds) !=
+            hipSuccess ||
+        lc.occ < 1)
+      lc.occ = 1;
+    lc.share = 0;
+    lc.ready = 1;
   }
+  const size_t lds = lc.lds;
+  int64_t grid = a.n_tiles;
+  if (PERSIST) grid = std::min<int64_t>(a.n_tiles, (int64_t)lc.occ * p->cu_count);
   if (grid < 1) return GNA_OK;
   if (grid > 0x7fffffffLL / sh.threads)
     return fail(GNA_E_UNSUPPORTED, "%lld tiles exceed one launch; use the persistent shape",

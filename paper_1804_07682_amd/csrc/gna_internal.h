@@ -116,7 +116,19 @@ struct gna_plan {
   gna::Shape shape;
   int64_t n_tiles;        // fitset: tiles in the queue; chain: tiles per point
   int cu_count;
-  size_t lds_limit;
+  size_t lds_limit;       // LDS budget of the generic kernel (64 KB)
+  size_t lds_device;      // LDS per work-group the device allows (160 KB on gfx950)
+  int share_phases;       // scan kernel may share phase terms across a tile
+  // Launch decisions that depend only on the plan and its shape (dynamic LDS,
+  // work-groups per CU, whether the shared-phase scan kernel got its LDS),
+  // made at the first launch without / with the gradient; apply_shape clears
+  // them.  Keeps attribute and occupancy queries off the evaluation path.
+  struct LaunchCache {
+    int ready;
+    int share;
+    size_t lds;
+    int occ;
+  } launch_cache[2];
   char arch[64];
   unsigned char* ws;
   size_t ws_bytes;

@@ -199,13 +199,16 @@ __device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
   return k;
 }
 
-// P_ee and its four parameter derivatives at phase-per-eV^2 q = (K L) / E.
-// Each phase's terms are folded into P and the tangents as soon as they are
-// computed, which keeps few values live at once.
-template <class R, bool GRAD>
-__device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R dP[4]) {
-  const R qr = to_r<R>(q);
-  const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
+// P_ee and its four parameter derivatives at phase-per-eV^2 q, with the
+// trigonometric terms of phase i (0: phi21, 1: phi31, 2: phi32) given by
+// terms(i).  Each phase's terms are folded into P and the tangents as soon as
+// they are available, which keeps few values live at once; every caller, be
+// it computing the terms in place or reading them from a table, performs the
+// same operations in the same order and so gets the same bits.
+template <class R, bool GRAD, class Terms>
+__device__ __forceinline__ void pee_accumulate(const PeeCoef<R>& k, R qr, Terms terms, R& P,
+                                               R dP[4]) {
+  const PhaseTerms<R> t21 = terms(0);
   R p = rfma_t<R>(k.A, t21.C, k.K0);
   R d0 = R(0), d1 = R(0), d2 = R(0), d3 = R(0);
   if (GRAD) {
@@ -213,14 +216,14 @@ __device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R
     d2 = -(k.dA12 * t21.S);
     d3 = -(k.dA13 * t21.S);
   }
-  const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
+  const PhaseTerms<R> t31 = terms(1);
   p = rfma_t<R>(k.B1, t31.C, p);
   if (GRAD) {
     d1 = -(k.B1 * t31.T);
     d2 = rfma_t<R>(k.B, t31.S, d2);
     d3 = d3 - k.dB13 * (k.c12 * t31.S);
   }
-  const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
+  const PhaseTerms<R> t32 = terms(2);
   P = rfma_t<R>(k.B2, t32.C, p);
   if (GRAD) {
     const R bt = k.B2 * t32.T;
@@ -229,6 +232,17 @@ __device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R
     dP[2] = d2 - k.B * t32.S;
     dP[3] = d3 - k.dB13 * (k.s12 * t32.S);
   }
+}
+
+// P_ee and its four parameter derivatives at phase-per-eV^2 q = (K L) / E.
+template <class R, bool GRAD>
+__device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R dP[4]) {
+  pee_accumulate<R, GRAD>(
+      k, to_r<R>(q),
+      [&](int i) {
+        return phase_terms<R>((i == 0 ? k.dm21 : i == 1 ? k.dm31 : k.dm32) * q);
+      },
+      P, dP);
 }
 
 }  // namespace gna

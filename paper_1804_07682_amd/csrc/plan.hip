@@ -441,6 +441,7 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
     p->n_tiles = (int64_t)tiles.size();
   }
   p->shape = sh;
+  p->launch_cache[0].ready = p->launch_cache[1].ready = 0;
   if (p->ws) {
     int rc = check_hip(hipMemcpyAsync(p->ws + p->lay.probs, p->probs.data(),
                                       sizeof(ProbDev) * p->probs.size(), hipMemcpyHostToDevice, s),
@@ -508,6 +509,7 @@ int device_limits(gna_plan* p) {
   // Host-only sizing must not touch the device: defaults for gfx950.
   p->cu_count = 256;
   p->lds_limit = 64 * 1024;
+  p->lds_device = 64 * 1024;
   std::snprintf(p->arch, sizeof(p->arch), "gfx950");
   return GNA_OK;
 }
@@ -535,6 +537,8 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       return fail(GNA_E_INVAL, "opts.persistent = %d not 0/1", opts->persistent);
     if (opts->smear_mfma < -1 || opts->smear_mfma > 3)
       return fail(GNA_E_INVAL, "opts.smear_mfma = %d not in -1..3", opts->smear_mfma);
+    if (opts->no_shared_phases < 0 || opts->no_shared_phases > 1)
+      return fail(GNA_E_INVAL, "opts.no_shared_phases = %d not 0/1", opts->no_shared_phases);
   }
   for (int i = 0; i < n_probs; ++i) {
     rc = validate_problem(problems + i, i);
@@ -550,6 +554,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->model = *model;
   p->max_bins = 0;
   p->ws = nullptr;
+  p->share_phases = (opts && opts->no_shared_phases) ? 0 : 1;
   device_limits(p);
   int64_t pts = 0, bins = 0, edges = 0, Ls = 0, slices = 0, band = 0;
   for (int i = 0; i < n_probs; ++i) {
@@ -647,6 +652,7 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
   rc = check_hip(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
   if (rc) return rc;
   p->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  p->lds_device = prop.sharedMemPerBlock > 0 ? (size_t)prop.sharedMemPerBlock : 64 * 1024;
   std::snprintf(p->arch, sizeof(p->arch), "%s", prop.gcnArchName);
   p->ws = (unsigned char*)ws;
   p->ws_bytes = ws_bytes;

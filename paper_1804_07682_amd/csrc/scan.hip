@@ -75,11 +75,16 @@ struct ScanArgs {
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Per-bin sums of the phase terms that a tile of points with common
+// (dm2_21, dm2_31) shares; see the kernel.
+constexpr int kTab = 10;
+
 template <class R>
-__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves) {
+__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, int share = 0) {
   return a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
          a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
-         a16((size_t)nwaves * kScanN * 6 * 8);
+         a16((size_t)nwaves * kScanN * 6 * 8) +
+         (share ? a16((size_t)mt * 16 * kTab * sizeof(R)) : 0);
 }
 
 template <class T>
@@ -92,7 +97,22 @@ __device__ __forceinline__ T xor_sum_16_32(T v) {
 // WPE: wavefronts per SIMD the register allocation must allow (2 = the
 // natural ~240-register allocation of the FP64 gradient variant; 3 and 4
 // trade spills of the per-bin sums for occupancy; the autotuner chooses).
-template <class R, bool GRAD, int NT, int WPE>
+//
+// SHARE: tiles whose points all have the same (dm2_21, dm2_31) take the
+// shared-phase path.  The phases depend only on dm2, E and L (a transformation
+// is recomputed only when its own inputs change, Sec. 2), and P_ee and its
+// tangents are linear in the per-point coefficients (K0, A, B1, B2 and the
+// tangent weights).  So the work-group forms, once per bin j, the sums over
+// the bin's quadrature points k and baselines r of f_k w_r times
+//   1, cos^2 phi21, cos^2 phi31, cos^2 phi32          (for mu)
+//   q sin 2phi21, q sin 2phi31, q sin 2phi32,          (for d/d dm2)
+//   sin^2 phi21, sin^2 phi31, sin^2 phi32              (for d/d s12, s13)
+// and each point's mu_j and J_jc are a few products of its coefficients with
+// that row.  The sums are taken in another order than the per-point path
+// (sum, then combine), so results agree to rounding, not bit for bit.  A
+// separate instantiation, so that the per-point kernel keeps its own register
+// allocation; tiles that do not share still take the per-point path.
+template <class R, bool GRAD, int NT, int WPE, bool SHARE>
 __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   using A4 = typename Acc<R>::T;
   constexpr int NW = NT / kWave;
@@ -113,6 +133,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   R* bb = reinterpret_cast<R*>(cur);  // [nbp][16] GEMM B operand
   cur += a16((size_t)nbp * kScanN * sizeof(R));
   double* red = reinterpret_cast<double*>(cur);  // [NW][16][6]
+  cur += a16((size_t)NW * kScanN * 6 * 8);
+  R* tab = reinterpret_cast<R*>(cur);  // [nbp][kTab] per-bin phase sums (SHARE only)
 
   const int tid = threadIdx.x;
   for (int i = tid; i < nL * nq; i += NT) q_s[i] = a.qtab[i];
@@ -126,6 +148,10 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int krow = lane >> 4;        // k index of this lane in an MFMA operand
   const int ntiles = (a.B + kScanN - 1) / kScanN;
+  // Lanes per bin for the shared sums: a power of two, at most 16.
+  int G = 1;
+  while (G < 16 && 2 * G * nb <= NT) G *= 2;
+  const int items = a.ppb * nL;
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int p_raw = tile * kScanN + n;
@@ -135,41 +161,102 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
     const PeeCoef<R> k = pee_coef<R>(th);
     const double norm = th[4];
 
+    bool shared = false;
+    if (SHARE) {
+      const double* t0 = a.params + 5 * (int64_t)tile * kScanN;
+      shared = __syncthreads_and(th[0] == t0[0] && th[1] == t0[1]) != 0;
+    }
+
     // ---- 1. point pass ------------------------------------------------------
     R mu0[PPT];
     R J0[PPT][4];
-#pragma clang loop unroll(full)
-    for (int m = 0; m < PPT; ++m) {
-      const int j = bg + NG * m;
-      R mu = R(0);
-      R J[4] = {R(0), R(0), R(0), R(0)};
-      if (j < nb) {
-        for (int kk = 0; kk < a.ppb; ++kk) {
-          const int kq = j * a.ppb + kk;
-          const R fk = f_s[kq];
-          R pb = R(0);
-          R dpb[4] = {R(0), R(0), R(0), R(0)};
-          for (int r = 0; r < nL; ++r) {
-            R P, dP[4];
-            pee_point<R, GRAD>(k, q_s[r * nq + kq], P, dP);
-            const R wr = (R)w_s[r];
-            pb = rfma_t<R>(wr, P, pb);
-            if (GRAD) {
+    if (SHARE && shared) {
+      // Per-bin phase sums: G lanes split the bin's (k, r) items, then fold.
+      for (int j0 = 0; j0 < nb; j0 += NT / G) {
+        const int j = j0 + tid / G, sub = tid & (G - 1);
+        R sum[kTab];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+        for (int c = 0; c < kTab; ++c) sum[c] = R(0);
+        if (j < nb) {
+          for (int it = sub; it < items; it += G) {
+            const int kk = it / nL, r = it - kk * nL;
+            const int kq = j * a.ppb + kk;
+            const double q = q_s[r * nq + kq];
+            const R fw = f_s[kq] * (R)w_s[r];
+            const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
+            const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
+            const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
+            sum[0] += fw;
+            sum[1] = rfma_t<R>(fw, t21.C, sum[1]);
+            sum[2] = rfma_t<R>(fw, t31.C, sum[2]);
+            sum[3] = rfma_t<R>(fw, t32.C, sum[3]);
+            if (GRAD) {
+              const R fq = fw * to_r<R>(q);
+              sum[4] = rfma_t<R>(fq, t21.T, sum[4]);
+              sum[5] = rfma_t<R>(fq, t31.T, sum[5]);
+              sum[6] = rfma_t<R>(fq, t32.T, sum[6]);
+              sum[7] = rfma_t<R>(fw, t21.S, sum[7]);
+              sum[8] = rfma_t<R>(fw, t31.S, sum[8]);
+              sum[9] = rfma_t<R>(fw, t32.S, sum[9]);
             }
           }
-          mu = rfma_t<R>(fk, pb, mu);
-          if (GRAD) {
+        }
+        for (int o = 1; o < G; o <<= 1) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
-          }
+          for (int c = 0; c < kTab; ++c) sum[c] += __shfl_xor(sum[c], o, kWave);
+        }
+        if (j < nb && sub == 0) {
+#pragma unroll
+          for (int c = 0; c < kTab; ++c) tab[j * kTab + c] = sum[c];
         }
       }
-      mu0[m] = mu;
+      __syncthreads();
+#pragma clang loop unroll(full)
+      for (int m = 0; m < PPT; ++m) {
+        const int j = bg + NG * m;
+        if (j < nbp) {
+          R mu = R(0);
+          if (j < nb) {
+            const R* t = tab + j * kTab;
+            mu = rfma_t<R>(k.B2, t[3], rfma_t<R>(k.B1, t[2], rfma_t<R>(k.A, t[1], k.K0 * t[0])));
+          }
+          bb[j * kScanN + n] = (R)norm * mu;
+        }
+      }
+    } else {
+#pragma clang loop unroll(full)
+      for (int m = 0; m < PPT; ++m) {
+        const int j = bg + NG * m;
+        R mu = R(0);
+        R J[4] = {R(0), R(0), R(0), R(0)};
+        if (j < nb) {
+          for (int kk = 0; kk < a.ppb; ++kk) {
+            const int kq = j * a.ppb + kk;
+            const R fk = f_s[kq];
+            R pb = R(0);
+            R dpb[4] = {R(0), R(0), R(0), R(0)};
+            for (int r = 0; r < nL; ++r) {
+              R P, dP[4];
+              pee_point<R, GRAD>(k, q_s[r * nq + kq], P, dP);
+              const R wr = (R)w_s[r];
+              pb = rfma_t<R>(wr, P, pb);
+              if (GRAD) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
-      if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
+                for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+              }
+            }
+            mu = rfma_t<R>(fk, pb, mu);
+            if (GRAD) {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
+            }
+          }
+        }
+        mu0[m] = mu;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
+        if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
+      }
     }
     __syncthreads();
 
@@ -258,15 +345,37 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
       }
       __syncthreads();
 
-      // ---- 5. gradient from the point-pass registers ------------------------------
+      // ---- 5. gradient from the point-pass registers (or the shared sums) --------
+      if (SHARE && shared) {
 #pragma clang loop unroll(full)
-      for (int m = 0; m < PPT; ++m) {
-        const int j = bg + NG * m;
-        if (j < nb) {
-          const double gm = (double)bb[j * kScanN + n];
+        for (int m = 0; m < PPT; ++m) {
+          const int j = bg + NG * m;
+          if (j < nb) {
+            const double gm = (double)bb[j * kScanN + n];
+            const R* t = tab + j * kTab;
+            const R mu =
+                rfma_t<R>(k.B2, t[3], rfma_t<R>(k.B1, t[2], rfma_t<R>(k.A, t[1], k.K0 * t[0])));
+            const R j0 = rfma_t<R>(k.B2, t[6], -(k.A * t[4]));
+            const R j1 = -rfma_t<R>(k.B1, t[5], k.B2 * t[6]);
+            const R j2 = rfma_t<R>(k.B, t[8], -(k.dA12 * t[7])) - k.B * t[9];
+            const R j3 = -(k.dA13 * t[7]) - k.dB13 * rfma_t<R>(k.c12, t[8], k.s12 * t[9]);
+            g[0] += gm * (double)j0;
+            g[1] += gm * (double)j1;
+            g[2] += gm * (double)j2;
+            g[3] += gm * (double)j3;
+            g[4] += gm * (double)mu;
+          }
+        }
+      } else {
+#pragma clang loop unroll(full)
+        for (int m = 0; m < PPT; ++m) {
+          const int j = bg + NG * m;
+          if (j < nb) {
+            const double gm = (double)bb[j * kScanN + n];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) g[c] += gm * (double)J0[m][c];
-          g[4] += gm * (double)mu0[m];
+            for (int c = 0; c < 4; ++c) g[c] += gm * (double)J0[m][c];
+            g[4] += gm * (double)mu0[m];
+          }
         }
       }
 #pragma unroll
@@ -373,18 +482,44 @@ int scan_threads(const gna_plan* p) {
   return 0;
 }
 
+template <class R, bool GRAD, int NT, int WPE, bool SHARE>
+int launch_scan_k(gna_plan* p, const ScanArgs<R>& a, const gna_plan::LaunchCache& lc,
+                  hipStream_t s) {
+  const int ntiles = (a.B + kScanN - 1) / kScanN;
+  const int grid = std::max(1, std::min(ntiles, lc.occ * p->cu_count));
+  hipLaunchKernelGGL((scan_kernel<R, GRAD, NT, WPE, SHARE>), dim3(grid), dim3(NT), lc.lds, s, a);
+  return check_hip(hipGetLastError(), "scan_kernel launch");
+}
+
 template <class R, bool GRAD, int NT, int WPE>
 int launch_scan_t(gna_plan* p, const ScanArgs<R>& a, hipStream_t s) {
-  const int nw = NT / 64;
-  const size_t lds = scan_lds<R>(a.nL, a.nq, a.mt, nw);
-  auto kern = scan_kernel<R, GRAD, NT, WPE>;
-  int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, NT, lds) != hipSuccess || occ < 1)
-    occ = 1;
-  const int ntiles = (a.B + kScanN - 1) / kScanN;
-  const int grid = std::max(1, std::min(ntiles, occ * p->cu_count));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, a);
-  return check_hip(hipGetLastError(), "scan_kernel launch");
+  gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
+  if (!lc.ready) {
+    const int nw = NT / 64;
+    // The shared-phase kernel needs LDS beyond 64 KB: ask for it, else go without.
+    lc.share = 0;
+    if (p->share_phases) {
+      const size_t big = scan_lds<R>(a.nL, a.nq, a.mt, nw, 1);
+      if (big <= p->lds_device &&
+          hipFuncSetAttribute((const void*)scan_kernel<R, GRAD, NT, WPE, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)big) == hipSuccess)
+        lc.share = 1;
+      else
+        (void)hipGetLastError();
+    }
+    lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share);
+    lc.occ = 0;
+    const hipError_t e =
+        lc.share ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &lc.occ, scan_kernel<R, GRAD, NT, WPE, true>, NT, lc.lds)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &lc.occ, scan_kernel<R, GRAD, NT, WPE, false>, NT, lc.lds);
+    if (e != hipSuccess || lc.occ < 1) lc.occ = 1;
+    lc.ready = 1;
+  }
+  return lc.share ? launch_scan_k<R, GRAD, NT, WPE, true>(p, a, lc, s)
+                  : launch_scan_k<R, GRAD, NT, WPE, false>(p, a, lc, s);
 }
 
 template <class R>

@@ -78,15 +78,24 @@ def test_scan_without_gradient(cfg0):
 
 
 def test_scan_deterministic_and_batch_invariant(cfg0):
+    """Same batch, same bits.  With per-point phases a point's result does not
+    depend on its batch neighbours at all; with shared phases a tile that
+    shares sums in another order, so neighbours change it only by rounding."""
     P = W.config3_params(4, 16)
     plan = _plan(cfg0, 64)
     a = _eval(plan, P)
     b = _eval(plan, P)
     for k in a:
         assert np.array_equal(a[k], b[k])
-    # A point's result does not depend on its batch neighbours.
     c = _eval(plan, P[[5, 0, 63]])
-    assert np.array_equal(c["chi2"], a["chi2"][[5, 0, 63]])
+    assert np.max(rel_err(c["chi2"], a["chi2"][[5, 0, 63]])) <= 1e-13
+    import paper_1804_07682_amd as gna
+    own = gna.Chain(cfg0, MODEL, max_batch=64, opts={"smear_mfma": 1, "no_shared_phases": 1},
+                    device=DEV)
+    a = _eval(own, P)
+    c = _eval(own, P[[5, 0, 63]])
+    for k in ("chi2", "grad"):
+        assert np.array_equal(c[k], a[k][[5, 0, 63]])
 
 
 def test_scan_domain_error(cfg0):
@@ -130,3 +139,69 @@ def test_scan_odd_geometry(cfg0):
     assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
     assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
     assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+
+
+def _plan_share(problem, B, prec, share):
+    import paper_1804_07682_amd as gna
+    return gna.Chain(problem, MODEL, max_batch=B, prec=prec,
+                     opts={"smear_mfma": 1, "no_shared_phases": 0 if share else 1}, device=DEV)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_shared_phase_tiles_match_per_point_path(cfg0, prec):
+    """Tiles whose points share (dm2_21, dm2_31) form per-bin phase sums once;
+    the results agree with the per-point path to rounding."""
+    P = W.config3_params(4, 64)  # every tile of 16 shares dm2_31
+    a = _eval(_plan_share(cfg0, 256, prec, True), P)
+    b = _eval(_plan_share(cfg0, 256, prec, False), P)
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    assert np.max(rel_err(a["pred"], b["pred"])) <= tol
+    assert np.max(rel_err(a["chi2"], b["chi2"])) <= tol * 10
+    assert np.max(grad_error(a["grad"], b["grad"], P, b["chi2"])) <= tol * 100
+
+
+# Bin counts that give 16, 4 and 2 lanes per bin in the shared sums, and the
+# 256-bin maximum of the scan kernel; several baselines and sub-intervals.
+@pytest.mark.parametrize("nb,order,L,n_sub", [
+    (20, 3, [52.5], 1),
+    (83, 4, [30.0, 52.5, 700.0], 2),
+    (240, 5, [52.5], 1),
+    (256, 2, [1.0, 1300.0], 1),
+])
+def test_shared_phase_tiles_match_oracle(nb, order, L, n_sub):
+    w = np.full(len(L), 1.0 / len(L))
+    pr = with_data(W.problem(W.uniform_edges(nb), order, L, w, n_sub=n_sub), MODEL, nb)
+    P = W.config3_params(2, 24)  # tiles 0 and 2 share, tile 1 straddles two dm2_31
+    plan = _plan_share(pr, P.shape[0], "fp64", True)
+    got = _eval(plan, P)
+    ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+
+
+def test_shared_and_unshared_tiles_match_oracle(cfg0):
+    P = W.config3_params(2, 16)  # 2 shared tiles
+    rng = np.random.default_rng(4)
+    Q = W.THETA0 * rng.uniform(0.9, 1.1, (16, 5))  # 1 unshared tile
+    M = W.config3_params(1, 16).copy()
+    M[5, 1] *= 1.01  # one point breaks the sharing of this tile
+    A = np.vstack([P, Q, M, W.config3_params(1, 3)])  # and a ragged last tile
+    for prec in ("fp64", "mixed"):
+        plan = _plan_share(cfg0, A.shape[0], prec, True)
+        got = _eval(plan, A)
+        ref = oracle.chain(cfg0, MODEL, A, grad=True, nu=True, n_threads=8)
+        tol = (FP64_RTOL, FP64_RTOL, FP64_RTOL) if prec == "fp64" else \
+            (MIXED_PRED_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL)
+        assert np.max(rel_err(got["pred"], ref["nu"])) <= tol[0]
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= tol[1]
+        assert np.max(grad_error(got["grad"], ref["grad"], A, ref["chi2"])) <= tol[2]
+
+
+def test_shared_phase_chi2_only(cfg0):
+    """The shared path without the gradient gives the same chi2 bits as with it."""
+    P = W.config3_params(2, 32)
+    plan = _plan_share(cfg0, 64, "fp64", True)
+    a = _eval(plan, P, grad=False, pred=False)
+    b = _eval(plan, P)
+    assert np.array_equal(a["chi2"], b["chi2"])

@@ -282,10 +282,9 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
     const double nu = (double)acc;
     const double d = dat[i];
     if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-    double term = nu - d;
-    if (d > 0.0) term += d * log(d / nu);
-    chi += term;
-    gnus[i] = (R)(2.0 * (1.0 - d / nu));
+    const double ratio = d / nu;
+    chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
+    gnus[i] = (R)(2.0 * (1.0 - ratio));
     if (pred) pred[i] = nu;
   }
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
@@ -406,6 +405,7 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
         lc.occ < 1)
       lc.occ = 1;
     lc.share = 0;
+    lc.rlds = 0;
     lc.ready = 1;
   }
   const size_t lds = lc.lds;

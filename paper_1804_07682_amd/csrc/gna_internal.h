@@ -126,9 +126,11 @@ struct gna_plan {
   struct LaunchCache {
     int ready;
     int share;
+    int rlds;
     size_t lds;
     int occ;
   } launch_cache[2];
+  int scan_nblk;          // 16x16 blocks in the band of R (scan kernel)
   char arch[64];
   unsigned char* ws;
   size_t ws_bytes;

@@ -64,8 +64,14 @@ struct ScanArgs {
   const double* data;  // [nb]
   const R* RA;         // [mt][mt][4][64]  R in A-operand order
   const R* RT;         // [mt][mt][4][64]  R^T in A-operand order
-  const int32_t* kbA;  // [mt][2] first / last nonzero k-block of row tile
-  const int32_t* kbT;  // [mt][2]
+  // Index tables, contiguous: kbA [mt][2] first / last nonzero k-block of
+  // row tile I of R; kbT [mt][2] the same for R^T; kbo [mt] index of row tile
+  // I's first block in the band; blkT [mt][mt] band index of block (I, J) at
+  // [J][I], or -1 where (I, J) lies outside row tile I's range.
+  const int32_t* meta;
+  const R* band;       // [nblk][16][kRowPad] the band of R, row tile by row tile
+  int32_t nblk;        // blocks in the band (kbA ranges, zero blocks inside included)
+  int32_t rlds;        // 1: the band is staged in LDS, 0: A operands come from RA / RT
   const double* params;
   double* chi2;
   double* grad;
@@ -74,17 +80,26 @@ struct ScanArgs {
 };
 
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline int scan_meta_ints(int mt) { return 5 * mt + mt * mt; }
 
 // Per-bin sums of the phase terms that a tile of points with common
 // (dm2_21, dm2_31) shares; see the kernel.
 constexpr int kTab = 10;
+// A 16x16 block of R staged in LDS: row-major with rows padded to 17 entries,
+// so that both R[i][k] (lanes along i) and R[k][i] (the transpose, lanes
+// along i) read distinct banks.
+constexpr int kRowPad = 17;
+constexpr int kBlk = 16 * kRowPad;
 
 template <class R>
-__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, int share = 0) {
-  return a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
+__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, int share = 0,
+                                           int rblocks = 0) {
+  return a16((size_t)scan_meta_ints(mt) * 4) + a16((size_t)kScanN * 5 * 8) +
+         a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
          a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
          a16((size_t)nwaves * kScanN * 6 * 8) +
-         (share ? a16((size_t)mt * 16 * kTab * sizeof(R)) : 0);
+         (share ? a16((size_t)mt * 16 * kTab * sizeof(R)) : 0) +
+         a16((size_t)rblocks * kBlk * sizeof(R));
 }
 
 template <class T>
@@ -122,6 +137,14 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int nL = a.nL, nq = a.nq, mt = a.mt, nb = a.nb, nbp = mt * 16;
   unsigned char* cur = lds;
+  int32_t* meta = reinterpret_cast<int32_t*>(cur);  // index tables (see ScanArgs)
+  cur += a16((size_t)scan_meta_ints(mt) * 4);
+  const int32_t* kbA_s = meta;
+  const int32_t* kbT_s = meta + 2 * mt;
+  const int32_t* kbo_s = meta + 4 * mt;
+  const int32_t* blkT_s = meta + 5 * mt;
+  double* p_s = reinterpret_cast<double*>(cur);  // [16][5] parameters of the tile
+  cur += a16((size_t)kScanN * 5 * 8);
   double* q_s = reinterpret_cast<double*>(cur);
   cur += a16((size_t)nL * nq * 8);
   R* f_s = reinterpret_cast<R*>(cur);
@@ -135,19 +158,33 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   double* red = reinterpret_cast<double*>(cur);  // [NW][16][6]
   cur += a16((size_t)NW * kScanN * 6 * 8);
   R* tab = reinterpret_cast<R*>(cur);  // [nbp][kTab] per-bin phase sums (SHARE only)
+  cur += SHARE ? a16((size_t)nbp * kTab * sizeof(R)) : 0;
+  R* Rs = reinterpret_cast<R*>(cur);  // [nblk][16][kRowPad] the band of R (if a.rlds)
 
   const int tid = threadIdx.x;
+  const int n = tid & (kScanN - 1);  // parameter point inside the tile (= GEMM column)
+  const int ntiles = (a.B + kScanN - 1) / kScanN;
+  // Every load of the prologue is independent, so their latencies overlap:
+  // the first tile's parameters, the index tables, the band of R (a plain
+  // copy: it is stored in its LDS layout) and the per-geometry tables.
+  if (tid < kScanN * 5) {
+    const int pp = min((int)blockIdx.x * kScanN + tid / 5, a.B - 1);
+    p_s[tid] = a.params[5 * (int64_t)pp + tid % 5];
+  }
+  for (int i = tid; i < scan_meta_ints(mt); i += NT) meta[i] = a.meta[i];
+  if (a.rlds) {
+#pragma unroll 4
+    for (int i = tid; i < a.nblk * kBlk; i += NT) Rs[i] = a.band[i];
+  }
   for (int i = tid; i < nL * nq; i += NT) q_s[i] = a.qtab[i];
   for (int i = tid; i < nq; i += NT) f_s[i] = a.f[i];
   for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
   for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
   __syncthreads();
 
-  const int n = tid & (kScanN - 1);  // parameter point inside the tile (= GEMM column)
   const int bg = tid >> 4;           // bin group
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int krow = lane >> 4;        // k index of this lane in an MFMA operand
-  const int ntiles = (a.B + kScanN - 1) / kScanN;
   // Lanes per bin for the shared sums: a power of two, at most 16.
   int G = 1;
   while (G < 16 && 2 * G * nb <= NT) G *= 2;
@@ -157,15 +194,17 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
     const int p_raw = tile * kScanN + n;
     const bool valid = p_raw < a.B;
     const int p = valid ? p_raw : a.B - 1;
-    const double* th = a.params + 5 * (int64_t)p;
-    const PeeCoef<R> k = pee_coef<R>(th);
-    const double norm = th[4];
+    double thv[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) thv[c] = p_s[5 * n + c];
+    const PeeCoef<R> k = pee_coef<R>(thv);
+    const double norm = thv[4];
 
+    // Each 16-lane group holds all 16 points of the tile, so a wave vote
+    // decides for the whole work-group (lanes past the end of the batch
+    // repeat its last point).
     bool shared = false;
-    if (SHARE) {
-      const double* t0 = a.params + 5 * (int64_t)tile * kScanN;
-      shared = __syncthreads_and(th[0] == t0[0] && th[1] == t0[1]) != 0;
-    }
+    if (SHARE) shared = __all(thv[0] == p_s[0] && thv[1] == p_s[1]) != 0;
 
     // ---- 1. point pass ------------------------------------------------------
     R mu0[PPT];
@@ -224,6 +263,10 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         }
       }
     } else {
+      // Per-point phases.  The SHARE kernel keeps only mu here and recomputes
+      // the tangents in the gradient pass, which keeps its registers for the
+      // shared path; the per-point kernel keeps the tangents in registers.
+      constexpr bool KEEP_J = GRAD && !SHARE;
 #pragma clang loop unroll(full)
       for (int m = 0; m < PPT; ++m) {
         const int j = bg + NG * m;
@@ -237,24 +280,26 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             R dpb[4] = {R(0), R(0), R(0), R(0)};
             for (int r = 0; r < nL; ++r) {
               R P, dP[4];
-              pee_point<R, GRAD>(k, q_s[r * nq + kq], P, dP);
+              pee_point<R, KEEP_J>(k, q_s[r * nq + kq], P, dP);
               const R wr = (R)w_s[r];
               pb = rfma_t<R>(wr, P, pb);
-              if (GRAD) {
+              if (KEEP_J) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
               }
             }
             mu = rfma_t<R>(fk, pb, mu);
-            if (GRAD) {
+            if (KEEP_J) {
 #pragma unroll
               for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
             }
           }
         }
         mu0[m] = mu;
+        if (KEEP_J) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
+          for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
+        }
         if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
       }
     }
@@ -267,14 +312,27 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
       acc[u] = A4{R(0), R(0), R(0), R(0)};
       const int I = wave + u * NW;
       if (I < mt) {
-        const int lo = a.kbA[2 * I], hi = a.kbA[2 * I + 1];
-        const R* At = a.RA + ((int64_t)I * mt) * 256 + lane;
-        for (int kb = lo; kb <= hi; ++kb) {
+        const int lo = kbA_s[2 * I], hi = kbA_s[2 * I + 1];
+        if (a.rlds) {
+          // A[i][k] = R[16 I + i][16 kb + k], i = lane & 15, k = 4 st + krow.
+          const R* Ab = Rs + kbo_s[I] * kBlk + (lane & 15) * kRowPad + krow;
+          for (int kb = lo; kb <= hi; ++kb) {
 #pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const R av = At[(kb * 4 + st) * 64];
-            const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-            acc[u] = Acc<R>::mfma(av, bv, acc[u]);
+            for (int st = 0; st < 4; ++st) {
+              const R av = Ab[(kb - lo) * kBlk + 4 * st];
+              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+              acc[u] = Acc<R>::mfma(av, bv, acc[u]);
+            }
+          }
+        } else {
+          const R* At = a.RA + ((int64_t)I * mt) * 256 + lane;
+          for (int kb = lo; kb <= hi; ++kb) {
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+              const R av = At[(kb * 4 + st) * 64];
+              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+              acc[u] = Acc<R>::mfma(av, bv, acc[u]);
+            }
           }
         }
       }
@@ -290,19 +348,18 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
       if (I < mt) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          // Branch-free over the padded rows (i >= nb: d = 0, nu = 0),
+          // which are masked; d = 0 takes ln 1 = 0.
           const int i = I * 16 + Acc<R>::row(krow, v);
-          if (i < nb) {
-            const double nu = (double)acc[u][v];
-            const double d = d_s[i];
-            if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-            double term = nu - d;
-            if (d > 0.0) term += d * log(d / nu);
-            chi += term;
-            bb[i * kScanN + n] = (R)(2.0 * (1.0 - d / nu));
-            if (a.pred && valid) a.pred[(int64_t)p * nb + i] = nu;
-          } else {
-            bb[i * kScanN + n] = R(0);
-          }
+          const bool in = i < nb;
+          const double nu = (double)acc[u][v];
+          const double d = d_s[i];
+          badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
+          const double ratio = d / nu;
+          const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
+          chi += in ? term : 0.0;
+          bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
+          if (a.pred && valid && in) a.pred[(int64_t)p * nb + i] = nu;
         }
       }
     }
@@ -322,14 +379,31 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         acc2[u] = A4{R(0), R(0), R(0), R(0)};
         const int J = wave + u * NW;
         if (J < mt) {
-          const int lo = a.kbT[2 * J], hi = a.kbT[2 * J + 1];
-          const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
-          for (int kb = lo; kb <= hi; ++kb) {
+          const int lo = kbT_s[2 * J], hi = kbT_s[2 * J + 1];
+          if (a.rlds) {
+            // A[i][k] = R^T[16 J + i][16 kb + k] = R[16 kb + k][16 J + i]: block
+            // (kb, J) of the band, read transposed; blocks outside row tile
+            // kb's range are zero.
+            for (int kb = lo; kb <= hi; ++kb) {
+              const int bi = blkT_s[J * mt + kb];
+              if (bi < 0) continue;
+              const R* Ab = Rs + bi * kBlk + krow * kRowPad + (lane & 15);
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-              const R av = At[(kb * 4 + st) * 64];
-              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-              acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+              for (int st = 0; st < 4; ++st) {
+                const R av = Ab[4 * st * kRowPad];
+                const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+                acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+              }
+            }
+          } else {
+            const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
+            for (int kb = lo; kb <= hi; ++kb) {
+#pragma unroll
+              for (int st = 0; st < 4; ++st) {
+                const R av = At[(kb * 4 + st) * 64];
+                const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+                acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+              }
             }
           }
         }
@@ -359,11 +433,39 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             const R j1 = -rfma_t<R>(k.B1, t[5], k.B2 * t[6]);
             const R j2 = rfma_t<R>(k.B, t[8], -(k.dA12 * t[7])) - k.B * t[9];
             const R j3 = -(k.dA13 * t[7]) - k.dB13 * rfma_t<R>(k.c12, t[8], k.s12 * t[9]);
-            g[0] += gm * (double)j0;
-            g[1] += gm * (double)j1;
-            g[2] += gm * (double)j2;
-            g[3] += gm * (double)j3;
-            g[4] += gm * (double)mu;
+            g[0] = dfma(gm, (double)j0, g[0]);
+            g[1] = dfma(gm, (double)j1, g[1]);
+            g[2] = dfma(gm, (double)j2, g[2]);
+            g[3] = dfma(gm, (double)j3, g[3]);
+            g[4] = dfma(gm, (double)mu, g[4]);
+          }
+        }
+      } else if (SHARE) {
+        // Tangents recomputed (same operations and order as the per-point
+        // kernel's point pass, so the same values).
+#pragma clang loop unroll(full)
+        for (int m = 0; m < PPT; ++m) {
+          const int j = bg + NG * m;
+          if (j < nb) {
+            R J[4] = {R(0), R(0), R(0), R(0)};
+            for (int kk = 0; kk < a.ppb; ++kk) {
+              const int kq = j * a.ppb + kk;
+              const R fk = f_s[kq];
+              R dpb[4] = {R(0), R(0), R(0), R(0)};
+              for (int r = 0; r < nL; ++r) {
+                R P, dP[4];
+                pee_point<R, true>(k, q_s[r * nq + kq], P, dP);
+                const R wr = (R)w_s[r];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+              }
+#pragma unroll
+              for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
+            }
+            const double gm = (double)bb[j * kScanN + n];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J[c], g[c]);
+            g[4] = dfma(gm, (double)mu0[m], g[4]);
           }
         }
       } else {
@@ -373,8 +475,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
           if (j < nb) {
             const double gm = (double)bb[j * kScanN + n];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) g[c] += gm * (double)J0[m][c];
-            g[4] += gm * (double)mu0[m];
+            for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J0[m][c], g[c]);
+            g[4] = dfma(gm, (double)mu0[m], g[4]);
           }
         }
       }
@@ -405,6 +507,11 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         for (int c = 0; c < 4; ++c) a.grad[5 * (int64_t)p + c] = k.bad ? NAN : norm * gs[c];
         a.grad[5 * (int64_t)p + 4] = k.bad ? NAN : gs[4];
       }
+    }
+    // Parameters of this group's next tile (every lane read p_s at the top).
+    if (tid < kScanN * 5) {
+      const int pn = min((tile + (int)gridDim.x) * kScanN + tid / 5, a.B - 1);
+      p_s[tid] = a.params[5 * (int64_t)pn + tid % 5];
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -442,8 +549,26 @@ __global__ void tile_kernel(const SliceDev* __restrict__ slices, const R* __rest
   out[idx] = v;
 }
 
+// Block (I, J) of R, listed in blist, into the band in its LDS layout
+// (row-major, rows padded to kRowPad; pads are 0).
+template <class R>
+__global__ void pack_band_kernel(const R* __restrict__ RA, const int32_t* __restrict__ blist,
+                                 int nblk, int mt, R* __restrict__ band) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nblk * kBlk) return;
+  const int b = (int)(idx / kBlk), w = (int)(idx % kBlk);
+  const int row = w / kRowPad, col = w % kRowPad;
+  R v = R(0);
+  if (col < 16) {
+    const int I = blist[2 * b], J = blist[2 * b + 1];
+    // RA holds A[i][k] = R[16 I + i][16 J + k] at step k / 4, lane i + 16 (k % 4).
+    v = RA[((int64_t)(I * mt + J) * 4 + col / 4) * 64 + row + 16 * (col % 4)];
+  }
+  band[idx] = v;
+}
+
 struct ScanLayout {
-  size_t RA, RT, kbA, kbT, qtab, total;
+  size_t RA, RT, meta, blist, band, qtab, total;
 };
 
 ScanLayout scan_layout(const gna_plan* p) {
@@ -460,8 +585,9 @@ ScanLayout scan_layout(const gna_plan* p) {
   };
   L.RA = take((size_t)mt * mt * 256 * rs);
   L.RT = take((size_t)mt * mt * 256 * rs);
-  L.kbA = take((size_t)mt * 2 * 4);
-  L.kbT = take((size_t)mt * 2 * 4);
+  L.meta = take((size_t)scan_meta_ints(mt) * 4);
+  L.blist = take((size_t)mt * mt * 2 * 4);
+  L.band = take((size_t)mt * mt * kBlk * rs);
   L.qtab = take((size_t)pd.n_L * nq * 8);
   L.total = off;
   return L;
@@ -491,24 +617,30 @@ int launch_scan_k(gna_plan* p, const ScanArgs<R>& a, const gna_plan::LaunchCache
   return check_hip(hipGetLastError(), "scan_kernel launch");
 }
 
+template <class R, bool GRAD, int NT, int WPE, bool SHARE>
+bool scan_lds_ok(const gna_plan* p, size_t bytes) {
+  if (bytes > p->lds_device) return false;
+  if (bytes <= 64 * 1024) return true;
+  if (hipFuncSetAttribute((const void*)scan_kernel<R, GRAD, NT, WPE, SHARE>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+    return true;
+  (void)hipGetLastError();
+  return false;
+}
+
 template <class R, bool GRAD, int NT, int WPE>
-int launch_scan_t(gna_plan* p, const ScanArgs<R>& a, hipStream_t s) {
+int launch_scan_t(gna_plan* p, ScanArgs<R> a, hipStream_t s) {
   gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
   if (!lc.ready) {
+    // LDS beyond 64 KB is asked for: first for the shared-phase table, then for
+    // the band of R (each only if it fits the device's LDS per work-group).
     const int nw = NT / 64;
-    // The shared-phase kernel needs LDS beyond 64 KB: ask for it, else go without.
-    lc.share = 0;
-    if (p->share_phases) {
-      const size_t big = scan_lds<R>(a.nL, a.nq, a.mt, nw, 1);
-      if (big <= p->lds_device &&
-          hipFuncSetAttribute((const void*)scan_kernel<R, GRAD, NT, WPE, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)big) == hipSuccess)
-        lc.share = 1;
-      else
-        (void)hipGetLastError();
-    }
-    lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share);
+    lc.share = p->share_phases &&
+               scan_lds_ok<R, GRAD, NT, WPE, true>(p, scan_lds<R>(a.nL, a.nq, a.mt, nw, 1, 0));
+    const size_t with_r = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share, a.nblk);
+    lc.rlds = a.nblk > 0 && (lc.share ? scan_lds_ok<R, GRAD, NT, WPE, true>(p, with_r)
+                                      : scan_lds_ok<R, GRAD, NT, WPE, false>(p, with_r));
+    lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share, lc.rlds ? a.nblk : 0);
     lc.occ = 0;
     const hipError_t e =
         lc.share ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -518,6 +650,7 @@ int launch_scan_t(gna_plan* p, const ScanArgs<R>& a, hipStream_t s) {
     if (e != hipSuccess || lc.occ < 1) lc.occ = 1;
     lc.ready = 1;
   }
+  a.rlds = lc.rlds;
   return lc.share ? launch_scan_k<R, GRAD, NT, WPE, true>(p, a, lc, s)
                   : launch_scan_k<R, GRAD, NT, WPE, false>(p, a, lc, s);
 }
@@ -542,8 +675,9 @@ int launch_scan_r(gna_plan* p, const double* params, int32_t B, double* chi2, do
   a.data = (const double*)(w + p->lay.data);
   a.RA = (const R*)(base + SL.RA);
   a.RT = (const R*)(base + SL.RT);
-  a.kbA = (const int32_t*)(base + SL.kbA);
-  a.kbT = (const int32_t*)(base + SL.kbT);
+  a.meta = (const int32_t*)(base + SL.meta);
+  a.band = (const R*)(base + SL.band);
+  a.nblk = p->scan_nblk;
   a.params = params;
   a.chi2 = chi2;
   a.grad = grad;
@@ -597,18 +731,35 @@ int build_scan_tables(gna_plan* p, hipStream_t s) {
       rowT_hi[J] = std::max(rowT_hi[J], i);
     }
   }
+  std::vector<int32_t> kbo(mt), blist, blkT((size_t)mt * mt, -1);
   for (int I = 0; I < mt; ++I) {
     kbA[2 * I] = colA_hi[I] >= 0 ? colA_lo[I] / 16 : 0;
     kbA[2 * I + 1] = colA_hi[I] >= 0 ? colA_hi[I] / 16 : -1;
     kbT[2 * I] = rowT_hi[I] >= 0 ? rowT_lo[I] / 16 : 0;
     kbT[2 * I + 1] = rowT_hi[I] >= 0 ? rowT_hi[I] / 16 : -1;
+    // The band's blocks, row tile by row tile, for staging in LDS.
+    kbo[I] = (int32_t)(blist.size() / 2);
+    for (int J = kbA[2 * I]; J <= kbA[2 * I + 1]; ++J) {
+      blkT[(size_t)J * mt + I] = (int32_t)(blist.size() / 2);
+      blist.push_back(I);
+      blist.push_back(J);
+    }
   }
-  int rc = check_hip(hipMemcpyAsync(base + SL.kbA, kbA.data(), kbA.size() * 4,
-                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync (kbA)");
+  const int nblk = (int)(blist.size() / 2);
+  p->scan_nblk = nblk;
+  std::vector<int32_t> meta;
+  meta.insert(meta.end(), kbA.begin(), kbA.end());
+  meta.insert(meta.end(), kbT.begin(), kbT.end());
+  meta.insert(meta.end(), kbo.begin(), kbo.end());
+  meta.insert(meta.end(), blkT.begin(), blkT.end());
+  int rc = check_hip(hipMemcpyAsync(base + SL.meta, meta.data(), meta.size() * 4,
+                                    hipMemcpyHostToDevice, s), "hipMemcpyAsync (scan index tables)");
   if (rc) return rc;
-  rc = check_hip(hipMemcpyAsync(base + SL.kbT, kbT.data(), kbT.size() * 4, hipMemcpyHostToDevice,
-                                s), "hipMemcpyAsync (kbT)");
-  if (rc) return rc;
+  if (nblk > 0) {
+    rc = check_hip(hipMemcpyAsync(base + SL.blist, blist.data(), blist.size() * 4,
+                                  hipMemcpyHostToDevice, s), "hipMemcpyAsync (blist)");
+    if (rc) return rc;
+  }
   const int64_t nq = (int64_t)nb * pd.ppb;
   const int64_t nqt = nq * pd.n_L;
   hipLaunchKernelGGL(qtab_kernel, dim3((unsigned)((nqt + 255) / 256)), dim3(256), 0, s,
@@ -629,7 +780,20 @@ int build_scan_tables(gna_plan* p, hipStream_t s) {
                          (float*)(base + (tr ? SL.RT : SL.RA)));
     if ((rc = check_hip(hipGetLastError(), "tile_kernel"))) return rc;
   }
-  // kbA / kbT host vectors die here.
+  if (nblk > 0) {
+    const int64_t nbe = (int64_t)nblk * kBlk;
+    const unsigned gb = (unsigned)((nbe + 255) / 256);
+    if (p->prec == GNA_FP64)
+      hipLaunchKernelGGL(pack_band_kernel<double>, dim3(gb), dim3(256), 0, s,
+                         (const double*)(base + SL.RA), (const int32_t*)(base + SL.blist), nblk,
+                         mt, (double*)(base + SL.band));
+    else
+      hipLaunchKernelGGL(pack_band_kernel<float>, dim3(gb), dim3(256), 0, s,
+                         (const float*)(base + SL.RA), (const int32_t*)(base + SL.blist), nblk,
+                         mt, (float*)(base + SL.band));
+    if ((rc = check_hip(hipGetLastError(), "pack_band_kernel"))) return rc;
+  }
+  // The host vectors die here.
   return check_hip(hipStreamSynchronize(s), "hipStreamSynchronize (scan tables)");
 }
 

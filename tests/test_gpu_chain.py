@@ -209,3 +209,21 @@ def test_adjoint_vs_central_differences(cfg0):
         h = 1e-6 * abs(th[c])
         fd = (got["chi2"][1 + 2 * c] - got["chi2"][2 + 2 * c]) / (2 * h)
         assert abs(fd - g[c]) * abs(th[c]) <= 1e-6 * max(abs(g[c] * th[c]), got["chi2"][0])
+
+
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_chi2_with_data_far_from_prediction(mfma):
+    """Counts from 0 to ~1e8 against the prediction: the chi^2 tail's
+    logarithm sees ratios d / nu over many binades (generic and MFMA kernels)."""
+    pr = dict(W.config0())
+    nu = oracle.prediction(pr, MODEL, W.THETA0)
+    rng = np.random.default_rng(17)
+    scale = 10.0 ** rng.uniform(-6, 6, nu.size)
+    data = np.round(nu * scale)
+    data[::7] = 0.0
+    pr["data"] = data
+    P = W.config3_params(2, 8)
+    ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
+    got = _eval(_plan(pr, B=P.shape[0], smear_mfma=mfma), P)
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL

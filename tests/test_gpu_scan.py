@@ -14,6 +14,13 @@ MODEL = W.model()
 MIXED_PRED_RTOL = 2e-6
 MIXED_CHI2_RTOL = 1e-5
 MIXED_GRAD_TOL = 1e-4
+# Geometries with baselines of hundreds of km: the dm2_21 and norm components
+# of the gradient cancel strongly there, and FP32 mu, tangents and smearing
+# (the mixed design) leave ~1e-4 in the scaled metric whichever order the sums
+# take (a float32 emulation of both the per-point and the shared order gives
+# 9e-5 on the 83-bin, 30 / 52.5 / 700 km case; FP64 trig terms and sums alone
+# still leave 5e-5).
+MIXED_GRAD_TOL_LONG_L = 3e-4
 
 
 @pytest.fixture(scope="module")
@@ -169,15 +176,19 @@ def test_shared_phase_tiles_match_per_point_path(cfg0, prec):
     (256, 2, [1.0, 1300.0], 1),
 ])
 def test_shared_phase_tiles_match_oracle(nb, order, L, n_sub):
+    """Also covers both homes of R's band: LDS (every size in mixed precision,
+    the small ones in FP64) and global memory (FP64 at 240 and 256 bins)."""
     w = np.full(len(L), 1.0 / len(L))
     pr = with_data(W.problem(W.uniform_edges(nb), order, L, w, n_sub=n_sub), MODEL, nb)
     P = W.config3_params(2, 24)  # tiles 0 and 2 share, tile 1 straddles two dm2_31
-    plan = _plan_share(pr, P.shape[0], "fp64", True)
-    got = _eval(plan, P)
     ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
-    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
-    assert np.max(rel_err(got["pred"], ref["nu"])) <= FP64_RTOL
-    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+    gtol = MIXED_GRAD_TOL_LONG_L if max(L) > 100 else MIXED_GRAD_TOL
+    for prec, tol in (("fp64", (FP64_RTOL,) * 3),
+                      ("mixed", (MIXED_PRED_RTOL, MIXED_CHI2_RTOL, gtol))):
+        got = _eval(_plan_share(pr, P.shape[0], prec, True), P)
+        assert np.max(rel_err(got["pred"], ref["nu"])) <= tol[0], prec
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= tol[1], prec
+        assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= tol[2], prec
 
 
 def test_shared_and_unshared_tiles_match_oracle(cfg0):

@@ -82,6 +82,19 @@ struct ScanArgs {
 __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15); }
 __host__ __device__ inline int scan_meta_ints(int mt) { return 5 * mt + mt * mt; }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// dst[0, bytes) = src[0, bytes) by the work-group, 16 bytes a lane, with
+// several loads in flight per lane (both 16-byte aligned; bytes % 16 == 0).
+template <int NT>
+__device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes) {
+  u32x4* d = reinterpret_cast<u32x4*>(dst);
+  const u32x4* g = reinterpret_cast<const u32x4*>(src);
+  const int n16 = (int)(bytes >> 4);
+#pragma unroll 8
+  for (int i = threadIdx.x; i < n16; i += NT) d[i] = g[i];
+}
+
 // Per-bin sums of the phase terms that a tile of points with common
 // (dm2_21, dm2_31) shares; see the kernel.
 constexpr int kTab = 10;
@@ -92,13 +105,12 @@ constexpr int kRowPad = 17;
 constexpr int kBlk = 16 * kRowPad;
 
 template <class R>
-__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, int share = 0,
-                                           int rblocks = 0) {
+__host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, int rblocks,
+                                           bool share) {
   return a16((size_t)scan_meta_ints(mt) * 4) + a16((size_t)kScanN * 5 * 8) +
          a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
          a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
-         a16((size_t)nwaves * kScanN * 6 * 8) +
-         (share ? a16((size_t)mt * 16 * kTab * sizeof(R)) : 0) +
+         a16((size_t)nwaves * kScanN * 6 * 8) + (share ? a16((size_t)mt * 16 * kTab * 8) : 0) +
          a16((size_t)rblocks * kBlk * sizeof(R));
 }
 
@@ -157,8 +169,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   cur += a16((size_t)nbp * kScanN * sizeof(R));
   double* red = reinterpret_cast<double*>(cur);  // [NW][16][6]
   cur += a16((size_t)NW * kScanN * 6 * 8);
-  R* tab = reinterpret_cast<R*>(cur);  // [nbp][kTab] per-bin phase sums (SHARE only)
-  cur += SHARE ? a16((size_t)nbp * kTab * sizeof(R)) : 0;
+  double* mm = reinterpret_cast<double*>(cur);  // [nbp][kTab] M = R T of a shared tile
+  cur += SHARE ? a16((size_t)nbp * kTab * 8) : 0;
   R* Rs = reinterpret_cast<R*>(cur);  // [nblk][16][kRowPad] the band of R (if a.rlds)
 
   const int tid = threadIdx.x;
@@ -172,11 +184,11 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
     p_s[tid] = a.params[5 * (int64_t)pp + tid % 5];
   }
   for (int i = tid; i < scan_meta_ints(mt); i += NT) meta[i] = a.meta[i];
-  if (a.rlds) {
-#pragma unroll 4
-    for (int i = tid; i < a.nblk * kBlk; i += NT) Rs[i] = a.band[i];
-  }
-  for (int i = tid; i < nL * nq; i += NT) q_s[i] = a.qtab[i];
+  if (a.rlds) copy16<NT>(Rs, a.band, (size_t)a.nblk * kBlk * sizeof(R));
+  if ((nL * nq) % 2 == 0)
+    copy16<NT>(q_s, a.qtab, (size_t)nL * nq * 8);
+  else
+    for (int i = tid; i < nL * nq; i += NT) q_s[i] = a.qtab[i];
   for (int i = tid; i < nq; i += NT) f_s[i] = a.f[i];
   for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
   for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
@@ -189,6 +201,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   int G = 1;
   while (G < 16 && 2 * G * nb <= NT) G *= 2;
   const int items = a.ppb * nL;
+  const int gq = G / nL, gr = G - gq * nL;
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int p_raw = tile * kScanN + n;
@@ -211,17 +224,38 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
     R J0[PPT][4];
     if (SHARE && shared) {
       // Per-bin phase sums: G lanes split the bin's (k, r) items, then fold.
+      // Each lane takes its items three at a time (independent chains that
+      // can overlap); slots past the end carry weight 0 and add exact zeros.
+      const int nslot = (items + G - 1) / G;
       for (int j0 = 0; j0 < nb; j0 += NT / G) {
         const int j = j0 + tid / G, sub = tid & (G - 1);
+        const bool jin = j < nb;
+        const int jc = jin ? j : nb - 1;
         R sum[kTab];
 #pragma unroll
         for (int c = 0; c < kTab; ++c) sum[c] = R(0);
-        if (j < nb) {
-          for (int it = sub; it < items; it += G) {
-            const int kk = it / nL, r = it - kk * nL;
-            const int kq = j * a.ppb + kk;
-            const double q = q_s[r * nq + kq];
-            const R fw = f_s[kq] * (R)w_s[r];
+        // Item it = kk nL + r; a lane's items step by G = gq nL + gr.
+        int kk = sub / nL, r = sub - kk * nL;
+        for (int s0 = 0; s0 < nslot; s0 += 3) {
+          int kks[3], rs[3];
+          bool ok[3];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            ok[u] = jin && sub + (s0 + u) * G < items;
+            kks[u] = ok[u] ? kk : 0;
+            rs[u] = ok[u] ? r : 0;
+            kk += gq;
+            r += gr;
+            if (r >= nL) {
+              r -= nL;
+              ++kk;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            const int kq = jc * a.ppb + kks[u];
+            const double q = q_s[rs[u] * nq + kq];
+            const R fw = ok[u] ? f_s[kq] * (R)w_s[rs[u]] : R(0);
             const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
             const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
             const PhaseTerms<R> t32 = phase_terms<R>(k.dm32 * q);
@@ -246,22 +280,12 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         }
         if (j < nb && sub == 0) {
 #pragma unroll
-          for (int c = 0; c < kTab; ++c) tab[j * kTab + c] = sum[c];
+          for (int c = 0; c < kTab; ++c) bb[j * kScanN + c] = sum[c];
         }
       }
-      __syncthreads();
-#pragma clang loop unroll(full)
-      for (int m = 0; m < PPT; ++m) {
-        const int j = bg + NG * m;
-        if (j < nbp) {
-          R mu = R(0);
-          if (j < nb) {
-            const R* t = tab + j * kTab;
-            mu = rfma_t<R>(k.B2, t[3], rfma_t<R>(k.B1, t[2], rfma_t<R>(k.A, t[1], k.K0 * t[0])));
-          }
-          bb[j * kScanN + n] = (R)norm * mu;
-        }
-      }
+      // The rest of the GEMM operand: columns kTab..15 and the padded rows.
+      for (int i = tid; i < nbp * kScanN; i += NT)
+        if ((i & (kScanN - 1)) >= kTab || i >= nb * kScanN) bb[i] = R(0);
     } else {
       // Per-point phases.  The SHARE kernel keeps only mu here and recomputes
       // the tangents in the gradient pass, which keeps its registers for the
@@ -337,156 +361,226 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         }
       }
     }
-    __syncthreads();  // every wave is done reading mu
+    __syncthreads();  // every wave is done reading the GEMM operand
 
-    // ---- 3. chi2 and gnu --------------------------------------------------------
     double chi = 0.0;
     bool badnu = false;
-#pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-      const int I = wave + u * NW;
-      if (I < mt) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // Branch-free over the padded rows (i >= nb: d = 0, nu = 0),
-          // which are masked; d = 0 takes ln 1 = 0.
-          const int i = I * 16 + Acc<R>::row(krow, v);
-          const bool in = i < nb;
-          const double nu = (double)acc[u][v];
-          const double d = d_s[i];
-          badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
-          const double ratio = d / nu;
-          const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
-          chi += in ? term : 0.0;
-          bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
-          if (a.pred && valid && in) a.pred[(int64_t)p * nb + i] = nu;
-        }
-      }
-    }
-    if (badnu && valid)
-      __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-    chi = xor_sum_16_32(chi);
-    if (lane < kScanN) red[(wave * kScanN + n) * 6] = chi;
-    __syncthreads();
-
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (GRAD) {
-      // ---- 4. gmu = R^T gnu ---------------------------------------------------
-      A4 acc2[TPW];
+    if (SHARE && shared) {
+      // ---- 3s. shared tiles: the accumulators hold M = R T, T the per-bin
+      // phase sums.  With c = (K0, A, B1, B2) of a point, nu = norm M c; with
+      // gnu = d chi2 / d nu, the gradient needs only the projections
+      // G_t = sum_i M_it gnu_i: gmu = R^T gnu and sum_j gmu_j T_jt = G_t, and
+      // mu_j and J_jc are linear in T_j.  Sums in FP64 (the products of FP32
+      // values are exact there).
 #pragma unroll
       for (int u = 0; u < TPW; ++u) {
-        acc2[u] = A4{R(0), R(0), R(0), R(0)};
-        const int J = wave + u * NW;
-        if (J < mt) {
-          const int lo = kbT_s[2 * J], hi = kbT_s[2 * J + 1];
-          if (a.rlds) {
-            // A[i][k] = R^T[16 J + i][16 kb + k] = R[16 kb + k][16 J + i]: block
-            // (kb, J) of the band, read transposed; blocks outside row tile
-            // kb's range are zero.
-            for (int kb = lo; kb <= hi; ++kb) {
-              const int bi = blkT_s[J * mt + kb];
-              if (bi < 0) continue;
-              const R* Ab = Rs + bi * kBlk + krow * kRowPad + (lane & 15);
+        const int I = wave + u * NW;
+        if (I < mt && n < kTab) {
 #pragma unroll
-              for (int st = 0; st < 4; ++st) {
-                const R av = Ab[4 * st * kRowPad];
-                const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-                acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
-              }
-            }
-          } else {
-            const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
-            for (int kb = lo; kb <= hi; ++kb) {
+          for (int v = 0; v < 4; ++v)
+            mm[(I * 16 + Acc<R>::row(krow, v)) * kTab + n] = (double)acc[u][v];
+        }
+      }
+      __syncthreads();
+      const double c0 = (double)k.K0, c1 = (double)k.A, c2 = (double)k.B1, c3 = (double)k.B2;
+      // Gp[0] = sum_i gnu_i s_i with s = M c (= nu / norm); Gp[t] = G_t for t >= 4.
+      double Gp[kTab];
 #pragma unroll
-              for (int st = 0; st < 4; ++st) {
-                const R av = At[(kb * 4 + st) * 64];
-                const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-                acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
-              }
+      for (int t = 0; t < kTab; ++t) Gp[t] = 0.0;
+      double nus[PPT];
+      // Branch-free over the bins (rows past nb are masked), so that the
+      // bins' division and logarithm chains can overlap (four at a time:
+      // more would not fit the registers).
+#pragma unroll 4
+      for (int m = 0; m < PPT; ++m) {
+        const int i = bg + NG * m;
+        const bool in = i < nb;
+        const double* Mi = mm + (in ? i : 0) * kTab;
+        const double si = dfma(c3, Mi[3], dfma(c2, Mi[2], dfma(c1, Mi[1], c0 * Mi[0])));
+        const double nu = norm * si;
+        const double d = in ? d_s[i] : 0.0;
+        badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
+        const double ratio = d / nu;
+        const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
+        chi += in ? term : 0.0;
+        if (GRAD) {
+          const double gn = in ? 2.0 * (1.0 - ratio) : 0.0;
+          Gp[0] = dfma(si, gn, Gp[0]);
+#pragma unroll
+          for (int t = 4; t < kTab; ++t) Gp[t] = dfma(Mi[t], gn, Gp[t]);
+        }
+        nus[m] = nu;
+      }
+      if (a.pred && valid) {
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+          const int i = bg + NG * m;
+          if (i < nb) a.pred[(int64_t)p * nb + i] = nus[m];
+        }
+      }
+      if (badnu && valid)
+        __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+      if (GRAD) {
+        const double b = (double)k.B;
+        g[0] = dfma(c3, Gp[6], -(c1 * Gp[4]));
+        g[1] = -dfma(c2, Gp[5], c3 * Gp[6]);
+        g[2] = dfma(b, Gp[8], -((double)k.dA12 * Gp[7])) - b * Gp[9];
+        g[3] = -((double)k.dA13 * Gp[7]) -
+               (double)k.dB13 * dfma((double)k.c12, Gp[8], (double)k.s12 * Gp[9]);
+        g[4] = Gp[0];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g[c] = xor_sum_16_32(g[c]);
+      }
+      chi = xor_sum_16_32(chi);
+      if (lane < kScanN) {
+        red[(wave * kScanN + n) * 6] = chi;
+        if (GRAD) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) red[(wave * kScanN + n) * 6 + 1 + c] = g[c];
+        }
+      }
+      __syncthreads();
+    } else {
+      // ---- 3. chi2 and gnu --------------------------------------------------------
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int I = wave + u * NW;
+        if (I < mt) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // Branch-free over the padded rows (i >= nb: d = 0, nu = 0),
+            // which are masked; d = 0 takes ln 1 = 0.
+            const int i = I * 16 + Acc<R>::row(krow, v);
+            const bool in = i < nb;
+            const double nu = (double)acc[u][v];
+            const double d = d_s[i];
+            badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
+            const double ratio = d / nu;
+            const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
+            chi += in ? term : 0.0;
+            bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
+          }
+        }
+      }
+      if (a.pred && valid) {
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+          const int I = wave + u * NW;
+          if (I < mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int i = I * 16 + Acc<R>::row(krow, v);
+              if (i < nb) a.pred[(int64_t)p * nb + i] = (double)acc[u][v];
             }
           }
         }
       }
-      __syncthreads();  // every wave is done reading gnu
-#pragma unroll
-      for (int u = 0; u < TPW; ++u) {
-        const int J = wave + u * NW;
-        if (J < mt) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) bb[(J * 16 + Acc<R>::row(krow, v)) * kScanN + n] = acc2[u][v];
-        }
-      }
+      if (badnu && valid)
+        __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+      chi = xor_sum_16_32(chi);
+      if (lane < kScanN) red[(wave * kScanN + n) * 6] = chi;
       __syncthreads();
 
-      // ---- 5. gradient from the point-pass registers (or the shared sums) --------
-      if (SHARE && shared) {
-#pragma clang loop unroll(full)
-        for (int m = 0; m < PPT; ++m) {
-          const int j = bg + NG * m;
-          if (j < nb) {
-            const double gm = (double)bb[j * kScanN + n];
-            const R* t = tab + j * kTab;
-            const R mu =
-                rfma_t<R>(k.B2, t[3], rfma_t<R>(k.B1, t[2], rfma_t<R>(k.A, t[1], k.K0 * t[0])));
-            const R j0 = rfma_t<R>(k.B2, t[6], -(k.A * t[4]));
-            const R j1 = -rfma_t<R>(k.B1, t[5], k.B2 * t[6]);
-            const R j2 = rfma_t<R>(k.B, t[8], -(k.dA12 * t[7])) - k.B * t[9];
-            const R j3 = -(k.dA13 * t[7]) - k.dB13 * rfma_t<R>(k.c12, t[8], k.s12 * t[9]);
-            g[0] = dfma(gm, (double)j0, g[0]);
-            g[1] = dfma(gm, (double)j1, g[1]);
-            g[2] = dfma(gm, (double)j2, g[2]);
-            g[3] = dfma(gm, (double)j3, g[3]);
-            g[4] = dfma(gm, (double)mu, g[4]);
-          }
-        }
-      } else if (SHARE) {
-        // Tangents recomputed (same operations and order as the per-point
-        // kernel's point pass, so the same values).
-#pragma clang loop unroll(full)
-        for (int m = 0; m < PPT; ++m) {
-          const int j = bg + NG * m;
-          if (j < nb) {
-            R J[4] = {R(0), R(0), R(0), R(0)};
-            for (int kk = 0; kk < a.ppb; ++kk) {
-              const int kq = j * a.ppb + kk;
-              const R fk = f_s[kq];
-              R dpb[4] = {R(0), R(0), R(0), R(0)};
-              for (int r = 0; r < nL; ++r) {
-                R P, dP[4];
-                pee_point<R, true>(k, q_s[r * nq + kq], P, dP);
-                const R wr = (R)w_s[r];
+      if (GRAD) {
+        // ---- 4. gmu = R^T gnu ---------------------------------------------------
+        A4 acc2[TPW];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+        for (int u = 0; u < TPW; ++u) {
+          acc2[u] = A4{R(0), R(0), R(0), R(0)};
+          const int J = wave + u * NW;
+          if (J < mt) {
+            const int lo = kbT_s[2 * J], hi = kbT_s[2 * J + 1];
+            if (a.rlds) {
+              // A[i][k] = R^T[16 J + i][16 kb + k] = R[16 kb + k][16 J + i]: block
+              // (kb, J) of the band, read transposed; blocks outside row tile
+              // kb's range are zero.
+              for (int kb = lo; kb <= hi; ++kb) {
+                const int bi = blkT_s[J * mt + kb];
+                if (bi < 0) continue;
+                const R* Ab = Rs + bi * kBlk + krow * kRowPad + (lane & 15);
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                  const R av = Ab[4 * st * kRowPad];
+                  const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+                  acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+                }
               }
+            } else {
+              const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
+              for (int kb = lo; kb <= hi; ++kb) {
 #pragma unroll
-              for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
+                for (int st = 0; st < 4; ++st) {
+                  const R av = At[(kb * 4 + st) * 64];
+                  const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+                  acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
+                }
+              }
             }
-            const double gm = (double)bb[j * kScanN + n];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J[c], g[c]);
-            g[4] = dfma(gm, (double)mu0[m], g[4]);
           }
         }
-      } else {
+        __syncthreads();  // every wave is done reading gnu
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+          const int J = wave + u * NW;
+          if (J < mt) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bb[(J * 16 + Acc<R>::row(krow, v)) * kScanN + n] = acc2[u][v];
+          }
+        }
+        __syncthreads();
+
+        // ---- 5. gradient from the point-pass registers (or recomputed) -----------
+        if (SHARE) {
+          // Tangents recomputed (same operations and order as the per-point
+          // kernel's point pass, so the same values).
 #pragma clang loop unroll(full)
-        for (int m = 0; m < PPT; ++m) {
-          const int j = bg + NG * m;
-          if (j < nb) {
-            const double gm = (double)bb[j * kScanN + n];
+          for (int m = 0; m < PPT; ++m) {
+            const int j = bg + NG * m;
+            if (j < nb) {
+              R J[4] = {R(0), R(0), R(0), R(0)};
+              for (int kk = 0; kk < a.ppb; ++kk) {
+                const int kq = j * a.ppb + kk;
+                const R fk = f_s[kq];
+                R dpb[4] = {R(0), R(0), R(0), R(0)};
+                for (int r = 0; r < nL; ++r) {
+                  R P, dP[4];
+                  pee_point<R, true>(k, q_s[r * nq + kq], P, dP);
+                  const R wr = (R)w_s[r];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J0[m][c], g[c]);
-            g[4] = dfma(gm, (double)mu0[m], g[4]);
+                  for (int c = 0; c < 4; ++c) dpb[c] = rfma_t<R>(wr, dP[c], dpb[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
+              }
+              const double gm = (double)bb[j * kScanN + n];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J[c], g[c]);
+              g[4] = dfma(gm, (double)mu0[m], g[4]);
+            }
+          }
+        } else {
+#pragma clang loop unroll(full)
+          for (int m = 0; m < PPT; ++m) {
+            const int j = bg + NG * m;
+            if (j < nb) {
+              const double gm = (double)bb[j * kScanN + n];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J0[m][c], g[c]);
+              g[4] = dfma(gm, (double)mu0[m], g[4]);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int c = 0; c < 5; ++c) g[c] = xor_sum_16_32(g[c]);
-      if (lane < kScanN) {
+        for (int c = 0; c < 5; ++c) g[c] = xor_sum_16_32(g[c]);
+        if (lane < kScanN) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) red[(wave * kScanN + n) * 6 + 1 + c] = g[c];
+          for (int c = 0; c < 5; ++c) red[(wave * kScanN + n) * 6 + 1 + c] = g[c];
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
 
     if (tid < kScanN && valid) {
@@ -601,8 +695,8 @@ int scan_threads(const gna_plan* p) {
   // 512 lanes: the gradient variant keeps mu0 / J0 of 8 bins in registers
   // (~240 VGPRs in FP64) without spilling; 1024 lanes would cap it at 128.
   for (int nt : {512}) {
-    const size_t b = fp64 ? scan_lds<double>(pd.n_L, nq, mt, nt / 64)
-                          : scan_lds<float>(pd.n_L, nq, mt, nt / 64);
+    const size_t b = fp64 ? scan_lds<double>(pd.n_L, nq, mt, nt / 64, 0, false)
+                          : scan_lds<float>(pd.n_L, nq, mt, nt / 64, 0, false);
     if (b <= std::min(kScanLdsMax, p->lds_limit)) return nt;
   }
   return 0;
@@ -632,15 +726,19 @@ template <class R, bool GRAD, int NT, int WPE>
 int launch_scan_t(gna_plan* p, ScanArgs<R> a, hipStream_t s) {
   gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
   if (!lc.ready) {
-    // LDS beyond 64 KB is asked for: first for the shared-phase table, then for
-    // the band of R (each only if it fits the device's LDS per work-group).
+    // The shared-phase kernel needs an FP64 copy of M = R T in LDS, and the
+    // band of R is staged in LDS when it fits; beyond 64 KB the kernel asks
+    // for the LDS (up to the device's per-work-group limit), else goes without.
     const int nw = NT / 64;
-    lc.share = p->share_phases &&
-               scan_lds_ok<R, GRAD, NT, WPE, true>(p, scan_lds<R>(a.nL, a.nq, a.mt, nw, 1, 0));
-    const size_t with_r = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share, a.nblk);
+    lc.share = p->share_phases;
+    const size_t with_r = scan_lds<R>(a.nL, a.nq, a.mt, nw, a.nblk, lc.share);
     lc.rlds = a.nblk > 0 && (lc.share ? scan_lds_ok<R, GRAD, NT, WPE, true>(p, with_r)
                                       : scan_lds_ok<R, GRAD, NT, WPE, false>(p, with_r));
-    lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.share, lc.rlds ? a.nblk : 0);
+    lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, lc.rlds ? a.nblk : 0, lc.share);
+    if (!lc.rlds && lc.share && !scan_lds_ok<R, GRAD, NT, WPE, true>(p, lc.lds)) {
+      lc.share = 0;
+      lc.lds = scan_lds<R>(a.nL, a.nq, a.mt, nw, 0, false);
+    }
     lc.occ = 0;
     const hipError_t e =
         lc.share ? hipOccupancyMaxActiveBlocksPerMultiprocessor(

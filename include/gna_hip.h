@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GNA_ABI_VERSION 2
+#define GNA_ABI_VERSION 3
 
 /* ---- status codes -------------------------------------------------------- */
 #define GNA_OK 0
@@ -267,9 +267,12 @@ int gna_fitset_eval(gna_plan* plan, const double* params_dev, double* chi2_dev,
  * Returns GNA_E_DOMAIN if any bit was set, else GNA_OK (or GNA_E_HIP).
  */
 int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
-/* Launch shape in use: writes 5 ints (threads, lanes_per_bin, chunks,
- * persistent, smear_mfma) and the number of tiles of one evaluation. */
-int gna_plan_shape(const gna_plan* plan, int32_t shape_out[5], int64_t* n_tiles);
+/* Launch shape in use: writes 6 ints (threads, lanes_per_bin, chunks,
+ * persistent, smear_mfma, shared_phases) and the number of tiles of one
+ * evaluation.  shared_phases is 1 when the MFMA kernel lets tiles with common
+ * (dm2_21, dm2_31) share their phases: the plan allows it (no_shared_phases
+ * = 0) and the shape asks for it (the autotuner tries both). */
+int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_t* n_tiles);
 /*
  * Project-written autotuner: times each candidate launch shape of this plan
  * on `stream` with HIP events (median of `reps` evaluations at params_dev,
@@ -281,7 +284,7 @@ int gna_plan_shape(const gna_plan* plan, int32_t shape_out[5], int64_t* n_tiles)
  */
 int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32_t B, double* chi2_dev,
                       double* grad_dev, int32_t reps, const char* cache_path, void* stream,
-                      int32_t shape_out[5]);
+                      int32_t shape_out[6]);
 /* Frees the host-side plan (the caller still owns the workspace). */
 int gna_plan_destroy(gna_plan* plan);
 

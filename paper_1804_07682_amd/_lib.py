@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libgna_hip.so")
 
-ABI_VERSION = 2  # the layout of the structs below
+ABI_VERSION = 3  # the layout of the structs below
 GNA_OK = 0
 GNA_E_INVAL = -1
 GNA_E_DOMAIN = -2

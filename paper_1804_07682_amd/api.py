@@ -32,6 +32,11 @@ def _stream(device=None) -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _raw_stream(device: torch.device) -> int:
+    """Handle of the current stream as a plain int (the per-evaluation path)."""
+    return torch.cuda.current_stream(device).cuda_stream
+
+
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
@@ -196,10 +201,11 @@ class _PlanBase:
         return word.value
 
     def shape(self):
-        s = (C.c_int32 * 5)()
+        s = (C.c_int32 * 6)()
         n = C.c_int64(0)
         check(load().gna_plan_shape(self._plan, s, C.byref(n)), "gna_plan_shape")
-        keys = ("threads", "lanes_per_bin", "chunks", "persistent", "smear_mfma")
+        keys = ("threads", "lanes_per_bin", "chunks", "persistent", "smear_mfma",
+                "shared_phases")
         d = dict(zip(keys, list(s)))
         d["n_tiles"] = n.value
         return d
@@ -223,7 +229,7 @@ class _PlanBase:
         B = params.shape[0]
         chi2 = torch.empty(B, dtype=torch.float64, device=self.device)
         grad = torch.empty((B, 5), dtype=torch.float64, device=self.device)
-        s = (C.c_int32 * 5)()
+        s = (C.c_int32 * 6)()
         path = None if cache_path is None else str(cache_path).encode()
         check(load().gna_plan_autotune(self._plan, _ptr(params), B, _ptr(chi2), _ptr(grad), reps,
                                        path, _stream(self.device), s), "gna_plan_autotune")
@@ -270,6 +276,7 @@ class Chain(_PlanBase):
                                    C.byref(o) if o else None, _ptr(ws), nbytes.value,
                                    _stream(self.device), C.byref(plan)), "gna_chain_create")
         self._plan = plan
+        self._eval_fn = lib.gna_chain_eval
 
     def eval(self, params: torch.Tensor, grad=True, pred=False, out=None):
         """chi^2 [B] (and grad [B, 5], pred [B, n_bins]) for params [B, 5]."""
@@ -290,8 +297,16 @@ class Chain(_PlanBase):
         pr = res.get("pred") if pred else None
         if pred and pr is None:
             pr = torch.empty((B, self.n_bins), dtype=torch.float64, device=dev)
-        check(load().gna_chain_eval(self._plan, _ptr(params), B, _ptr(chi2), _ptr(g), _ptr(pr),
-                                    _stream(dev)), "gna_chain_eval")
+        for t, nm, n in ((chi2, "chi2", B), (g, "grad", 5 * B), (pr, "pred", self.n_bins * B)):
+            if t is not None and (t.numel() < n or t.dtype != torch.float64 or not t.is_cuda
+                                  or not t.is_contiguous()):
+                raise ValueError(f"out[{nm!r}] must be a contiguous CUDA float64 tensor of "
+                                 f">= {n} elements")
+        st = self._eval_fn(self._plan, params.data_ptr(), B, chi2.data_ptr(),
+                           None if g is None else g.data_ptr(),
+                           None if pr is None else pr.data_ptr(), _raw_stream(dev))
+        if st:
+            check(st, "gna_chain_eval")
         res = {"chi2": chi2}
         if grad:
             res["grad"] = g

@@ -96,6 +96,7 @@ struct Layout {
 
 struct Shape {
   int threads = 256, G = 1, C = 1, persistent = 0, mfma = 0;
+  int share = 1;  // MFMA kernel: tiles with common dm2 share their phases (if the plan allows)
 };
 
 }  // namespace gna
@@ -118,7 +119,8 @@ struct gna_plan {
   int cu_count;
   size_t lds_limit;       // LDS budget of the generic kernel (64 KB)
   size_t lds_device;      // LDS per work-group the device allows (160 KB on gfx950)
-  int share_phases;       // scan kernel may share phase terms across a tile
+  int share_allowed;      // the plan's options allow phase sharing across a tile
+  int share_phases;       // the current shape shares (share_allowed && shape.share)
   // Launch decisions that depend only on the plan and its shape (dynamic LDS,
   // work-groups per CU, whether the shared-phase scan kernel got its LDS),
   // made at the first launch without / with the gradient; apply_shape clears

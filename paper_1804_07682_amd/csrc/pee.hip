@@ -2,7 +2,7 @@
 // P[i] = sum_r w_r P_ee(E[i]; L_r, theta).
 //
 // HBM-streaming kernel: 16-byte non-temporal loads of two energies per lane
-// and 16-byte (FP64) or 8-byte (mixed) stores; the probability needs only
+// and 16-byte (FP64) or 8-byte (mixed) stores, software-pipelined; the probability needs only
 // cos^2 of each phase, so one sin^2 polynomial per phase is evaluated
 // (cos^2 = 1 - sin^2 >= 1/2 on the reduced argument).  Phases and their
 // reduction are FP64 in both modes; q = KL / E comes from a refined
@@ -58,34 +58,57 @@ struct Vec2<float> {
   using T = fvec2;
 };
 
-// Each lane handles pairs p = tid, tid + stride, ...; two pairs per trip keep
-// two independent streams of FP64 work in flight per lane.
+// Two ways of walking the pairs (E[2p], E[2p+1]), both software-pipelined:
+// each lane issues the load of its next pair before evaluating the current
+// one, so HBM traffic overlaps the arithmetic.
+//  * grid-stride (mixed precision): pairs p, p + stride, ... with a grid of
+//    256 work-groups per CU;
+//  * chunked (FP64, whose evaluation is about twice as long): work-group b
+//    owns the contiguous pairs [b C, (b + 1) C) and its lanes stride by the
+//    group size, so each group streams one contiguous region.
+// Both measured on MI355X against a streaming copy of the same size.
+constexpr int64_t kPeeChunk = 2048;  // pairs per work-group in the chunked walk
+
 template <class R, bool ONE_L>
+__device__ __forceinline__ typename Vec2<R>::T pee_pair(const PeeArgs<R>& a, dvec2 e) {
+  typename Vec2<R>::T o;
+  o.x = pee_eval<R, ONE_L>(a, e.x);
+  o.y = pee_eval<R, ONE_L>(a, e.y);
+  return o;
+}
+
+// Pairs p0, p0 + step, ... below p1, pipelined.
+template <class R, bool ONE_L>
+__device__ __forceinline__ void pee_walk(const dvec2* __restrict__ E2,
+                                         typename Vec2<R>::T* __restrict__ P2,
+                                         const PeeArgs<R>& a, int64_t p0, int64_t p1,
+                                         int64_t step) {
+  if (p0 >= p1) return;
+  dvec2 cur = __builtin_nontemporal_load(E2 + p0);
+  for (int64_t p = p0;; p += step) {
+    const int64_t nx = p + step;
+    dvec2 nxt = cur;
+    if (nx < p1) nxt = __builtin_nontemporal_load(E2 + nx);
+    __builtin_nontemporal_store(pee_pair<R, ONE_L>(a, cur), P2 + p);
+    if (nx >= p1) break;
+    cur = nxt;
+  }
+}
+
+template <class R, bool ONE_L, bool CHUNKED>
 __global__ void __launch_bounds__(kPeeThreads)
     pee_kernel(const double* __restrict__ E, int64_t n, PeeArgs<R> a, R* __restrict__ P) {
   using V = typename Vec2<R>::T;
   const int64_t npairs = n >> 1;
-  const int64_t stride = (int64_t)gridDim.x * kPeeThreads;
-  int64_t p = (int64_t)blockIdx.x * kPeeThreads + threadIdx.x;
   const dvec2* E2 = reinterpret_cast<const dvec2*>(E);
   V* P2 = reinterpret_cast<V*>(P);
-  for (; p + stride < npairs; p += 2 * stride) {
-    const dvec2 e0 = __builtin_nontemporal_load(E2 + p);
-    const dvec2 e1 = __builtin_nontemporal_load(E2 + p + stride);
-    V o0, o1;
-    o0.x = pee_eval<R, ONE_L>(a, e0.x);
-    o0.y = pee_eval<R, ONE_L>(a, e0.y);
-    o1.x = pee_eval<R, ONE_L>(a, e1.x);
-    o1.y = pee_eval<R, ONE_L>(a, e1.y);
-    __builtin_nontemporal_store(o0, P2 + p);
-    __builtin_nontemporal_store(o1, P2 + p + stride);
-  }
-  if (p < npairs) {
-    const dvec2 e0 = __builtin_nontemporal_load(E2 + p);
-    V o0;
-    o0.x = pee_eval<R, ONE_L>(a, e0.x);
-    o0.y = pee_eval<R, ONE_L>(a, e0.y);
-    __builtin_nontemporal_store(o0, P2 + p);
+  if (CHUNKED) {
+    const int64_t b0 = (int64_t)blockIdx.x * kPeeChunk;
+    const int64_t b1 = b0 + kPeeChunk < npairs ? b0 + kPeeChunk : npairs;
+    pee_walk<R, ONE_L>(E2, P2, a, b0 + threadIdx.x, b1, kPeeThreads);
+  } else {
+    pee_walk<R, ONE_L>(E2, P2, a, (int64_t)blockIdx.x * kPeeThreads + threadIdx.x, npairs,
+                       (int64_t)gridDim.x * kPeeThreads);
   }
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) P[n - 1] = pee_eval<R, ONE_L>(a, E[n - 1]);
 }
@@ -124,18 +147,26 @@ int run_pee(const double* E, int64_t n, int32_t n_L, const double* L, const doub
     a.w[r] = (R)(wL ? wL[r] : 1.0 / n_L);
   }
   const int64_t npairs = n >> 1;
-  const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
-  // 256 groups per CU: a few pairs per lane and enough groups in flight to
-  // keep HBM busy (a smaller grid left the stream loop latency-bound).
-  const int64_t cap = (int64_t)cu_count() * 256;
-  const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
   const bool oneL = (n_L == 1 && (!wL || wL[0] == 1.0));
-  if (oneL)
-    hipLaunchKernelGGL((pee_kernel<R, true>), dim3(blocks), dim3(kPeeThreads), 0, s, E, n, a,
-                       (R*)P);
+  const bool chunked = sizeof(R) == 8;
+  int64_t blocks;
+  if (chunked) {
+    blocks = std::max<int64_t>(1, (npairs + kPeeChunk - 1) / kPeeChunk);
+  } else {
+    // 256 groups per CU: enough in flight to keep HBM busy.
+    const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
+    blocks = std::max<int64_t>(1, std::min(want, (int64_t)cu_count() * 256));
+  }
+  if (blocks > 0x7fffffffLL) return fail(GNA_E_UNSUPPORTED, "gna_pee: n = %lld too large", (long long)n);
+  const dim3 g((unsigned)blocks), t(kPeeThreads);
+  if (oneL && chunked)
+    hipLaunchKernelGGL((pee_kernel<R, true, true>), g, t, 0, s, E, n, a, (R*)P);
+  else if (oneL)
+    hipLaunchKernelGGL((pee_kernel<R, true, false>), g, t, 0, s, E, n, a, (R*)P);
+  else if (chunked)
+    hipLaunchKernelGGL((pee_kernel<R, false, true>), g, t, 0, s, E, n, a, (R*)P);
   else
-    hipLaunchKernelGGL((pee_kernel<R, false>), dim3(blocks), dim3(kPeeThreads), 0, s, E, n, a,
-                       (R*)P);
+    hipLaunchKernelGGL((pee_kernel<R, false, false>), g, t, 0, s, E, n, a, (R*)P);
   return check_hip(hipGetLastError(), "gna_pee launch");
 }
 
@@ -176,19 +207,22 @@ extern "C" int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double
 // ---------------------------------------------------------------------------
 // Streaming copy (the measured-bandwidth reference for the elementwise kernel
 // and the known-size calibration of the memory-traffic counters): 16-byte
-// non-temporal loads and stores, the same grid shape as the P_ee kernel.
+// non-temporal loads and stores, two per lane per trip, in the fastest of
+// the grid shapes measured on MI355X (512 lanes, 128 groups per CU).
 // ---------------------------------------------------------------------------
 namespace gna {
 namespace {
 
-__global__ void __launch_bounds__(kPeeThreads)
+constexpr int kCopyThreads = 512;
+
+__global__ void __launch_bounds__(kCopyThreads)
     copy_kernel(const double* __restrict__ src, int64_t n, double* __restrict__ dst) {
   typedef double v2 __attribute__((ext_vector_type(2)));
   const int64_t npairs = n >> 1;
-  const int64_t stride = (int64_t)gridDim.x * kPeeThreads;
+  const int64_t stride = (int64_t)gridDim.x * kCopyThreads;
   const v2* s2 = reinterpret_cast<const v2*>(src);
   v2* d2 = reinterpret_cast<v2*>(dst);
-  int64_t p = (int64_t)blockIdx.x * kPeeThreads + threadIdx.x;
+  int64_t p = (int64_t)blockIdx.x * kCopyThreads + threadIdx.x;
   for (; p + stride < npairs; p += 2 * stride) {
     const v2 a = __builtin_nontemporal_load(s2 + p);
     const v2 b = __builtin_nontemporal_load(s2 + p + stride);
@@ -211,9 +245,9 @@ extern "C" int gna_stream_copy(const double* src_dev, double* dst_dev, int64_t n
   if (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15)
     return fail(GNA_E_INVAL, "gna_stream_copy: pointers must be 16-byte aligned");
   const int64_t npairs = n >> 1;
-  const int64_t want = (npairs + kPeeThreads - 1) / kPeeThreads;
-  const int blocks = (int)std::max<int64_t>(1, std::min(want, (int64_t)cu_count() * 256));
-  hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(kPeeThreads), 0, (hipStream_t)stream, src_dev,
-                     n, dst_dev);
+  const int64_t want = (npairs + kCopyThreads - 1) / kCopyThreads;
+  const int blocks = (int)std::max<int64_t>(1, std::min(want, (int64_t)cu_count() * 128));
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(kCopyThreads), 0, (hipStream_t)stream,
+                     src_dev, n, dst_dev);
   return check_hip(hipGetLastError(), "gna_stream_copy launch");
 }

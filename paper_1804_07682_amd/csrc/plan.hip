@@ -379,11 +379,13 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
       }
     }
   if (p->kind == kChain && scan_supported(p)) {
-    for (int v = 1; v <= 3; ++v) {
-      Shape sh;
-      sh.mfma = v;
-      out.push_back(sh);
-    }
+    for (int v = 1; v <= 3; ++v)
+      for (int share = p->share_allowed; share >= 0; --share) {
+        Shape sh;
+        sh.mfma = v;
+        sh.share = share;
+        out.push_back(sh);
+      }
   }
   return out;
 }
@@ -441,6 +443,7 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
     p->n_tiles = (int64_t)tiles.size();
   }
   p->shape = sh;
+  p->share_phases = p->share_allowed && sh.share;
   p->launch_cache[0].ready = p->launch_cache[1].ready = 0;
   if (p->ws) {
     int rc = check_hip(hipMemcpyAsync(p->ws + p->lay.probs, p->probs.data(),
@@ -554,7 +557,8 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->model = *model;
   p->max_bins = 0;
   p->ws = nullptr;
-  p->share_phases = (opts && opts->no_shared_phases) ? 0 : 1;
+  p->share_allowed = (opts && opts->no_shared_phases) ? 0 : 1;
+  p->share_phases = p->share_allowed;
   device_limits(p);
   int64_t pts = 0, bins = 0, edges = 0, Ls = 0, slices = 0, band = 0;
   for (int i = 0; i < n_probs; ++i) {
@@ -830,7 +834,7 @@ extern "C" int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_sta
   return GNA_OK;
 }
 
-extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[5], int64_t* n_tiles) {
+extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_t* n_tiles) {
   clear_error();
   if (!plan) return fail(GNA_E_INVAL, "plan is NULL");
   if (shape_out) {
@@ -839,6 +843,7 @@ extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[5], int64_
     shape_out[2] = plan->shape.C;
     shape_out[3] = plan->shape.persistent;
     shape_out[4] = plan->shape.mfma;
+    shape_out[5] = plan->share_phases;
   }
   if (n_tiles) *n_tiles = plan->n_tiles;
   return GNA_OK;

@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_strings(lib):
-    assert lib.gna_abi_version() == 2
+    assert lib.gna_abi_version() == 3
     for code in (0, -1, -2, -3, -4, -5, 17):
         assert lib.gna_strerror(code)
     assert lib.gna_strerror(-4).decode().startswith("workspace")

@@ -56,6 +56,8 @@ def test_pee_multi_baseline_weights():
     got = _run(E, L)  # default weights 1/n_L
     ref = oracle.pee(E, L, TH, n_threads=8)
     assert np.max(rel_err(got, ref)) <= FP64_RTOL
+    gotm = _run(E, L, prec="mixed")  # the mixed kernel's several-baseline form
+    assert np.max(np.abs(gotm - ref)) <= MIXED_ATOL
 
 
 def test_pee_degenerate_cases():

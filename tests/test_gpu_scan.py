@@ -216,3 +216,34 @@ def test_shared_phase_chi2_only(cfg0):
     a = _eval(plan, P, grad=False, pred=False)
     b = _eval(plan, P)
     assert np.array_equal(a["chi2"], b["chi2"])
+
+
+def test_shape_reports_phase_sharing(cfg0):
+    import paper_1804_07682_amd as gna
+    assert _plan(cfg0, 16).shape()["shared_phases"] == 1
+    off = gna.Chain(cfg0, MODEL, max_batch=16, opts={"smear_mfma": 1, "no_shared_phases": 1},
+                    device=DEV)
+    assert off.shape()["shared_phases"] == 0
+
+
+@pytest.mark.parametrize("sharing_batch", [True, False])
+def test_scan_autotune_keeps_results(cfg0, sharing_batch, tmp_path):
+    """The autotuner also chooses whether tiles share their phases; whatever it
+    picks, the results stay within FP64 parity, and a cached choice is reused."""
+    import paper_1804_07682_amd as gna
+    if sharing_batch:
+        P = W.config3_params(4, 16)
+    else:
+        P = W.THETA0 * np.random.default_rng(9).uniform(0.9, 1.1, (64, 5))
+    Pt = torch.tensor(P, dtype=torch.float64, device=DEV)
+    cache = tmp_path / "tune.json"
+    plan = gna.Chain(cfg0, MODEL, max_batch=64, device=DEV)
+    shape = plan.autotune(Pt, reps=2, cache_path=cache)
+    assert "shared_phases" in shape
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+    again = gna.Chain(cfg0, MODEL, max_batch=64, device=DEV).autotune(Pt, reps=2,
+                                                                       cache_path=cache)
+    assert again == shape

@@ -129,9 +129,11 @@ class Timer:
 
     run() times `steps` calls back to back, bracketed by a synchronize and a
     pair of events only (no per-step work on the host, which would otherwise
-    show up as gaps between launches), then repeats `steps` calls with an
-    event pair around each to get the mean and median duration of one call on
-    the GPU."""
+    show up as gaps between launches): the host wall time and the event span
+    divided by `steps` (the launch period, which for a GPU-bound loop is the
+    kernel's average duration plus the dispatch gap).  It then repeats `steps`
+    calls with an event pair around each for the mean and median of single
+    calls (those events add a few microseconds of their own per call)."""
 
     def __init__(self, torch):
         self.torch = torch
@@ -149,6 +151,7 @@ class Timer:
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        self.period = e0.elapsed_time(e1) * 1e-3 / steps
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
         for a, b in ev:
@@ -185,10 +188,12 @@ def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup, share=True):
     out = {"chi2": torch.empty(P.shape[0], dtype=torch.float64, device=dev),
            "grad": torch.empty((P.shape[0], 5), dtype=torch.float64, device=dev)}
     fn = lambda: plan.eval(P, grad=True, out=out)
-    wall, kmean, kmed = timer.run(fn, steps, warmup)
+    wall, kpair, kmed = timer.run(fn, steps, warmup)
+    kmean = timer.period
     plan.status()
     flops = scan_flops(P.cpu().numpy(), 1200, 240, share)
-    return {"plan": plan, "pr": pr, "P": P, "wall": wall, "kernel_s": kmean, "kernel_med_s": kmed,
+    return {"plan": plan, "pr": pr, "P": P, "wall": wall, "kernel_s": kmean,
+            "event_pair_s": kpair, "event_pair_med_s": kmed,
             "evals_per_s": P.shape[0] * steps / wall, "shape": plan.shape(),
             "flops": flops, "tflops": flops / kmean / 1e12}
 
@@ -201,7 +206,8 @@ def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
     # Streaming rates ramp up over the first ~100 back-to-back launches on a
     # fresh allocation; the untimed warm-up covers that, so the figure is the
     # sustained one.
-    wall, kmean, _ = timer.run(fn, steps, STREAM_WARMUP)
+    wall, _, _ = timer.run(fn, steps, STREAM_WARMUP)
+    kmean = timer.period
     nbytes = n * (8 + out.element_size())
     res = {"evals_per_s": n * steps / wall, "kernel_ms": kmean * 1e3,
            "GBps": nbytes / kmean / 1e9, "bytes_per_eval": 8 + out.element_size()}
@@ -214,7 +220,8 @@ def copy_probe(gna, torch, timer, dev, n=10 ** 8, steps=20):
     """The library's streaming copy (16 B loads and stores, the P_ee grid shape)."""
     a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
     b = torch.empty_like(a)
-    wall, kmean, _ = timer.run(lambda: gna.gna_stream_copy(a, b), steps, STREAM_WARMUP)
+    timer.run(lambda: gna.gna_stream_copy(a, b), steps, STREAM_WARMUP)
+    kmean = timer.period
     return {"GBps": 16 * n / kmean / 1e9, "bytes": 16 * n, "kernel_ms": kmean * 1e3}
 
 
@@ -231,8 +238,9 @@ def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec)
     plan.autotune(P, reps=5)
     out = {"chi2": torch.empty(1, dtype=torch.float64, device=dev),
            "grad": torch.empty((1, 5), dtype=torch.float64, device=dev)}
-    wall, kmean, _ = timer.run(lambda: plan.eval(P, grad=True, out=out), steps, 10)
-    res = {"evals_per_s": steps / wall, "kernel_us": kmean * 1e6, "shape": plan.shape()}
+    wall, kpair, _ = timer.run(lambda: plan.eval(P, grad=True, out=out), steps, 10)
+    res = {"evals_per_s": steps / wall, "launch_period_us": timer.period * 1e6,
+           "event_pair_us": kpair * 1e6, "shape": plan.shape()}
     res["graph"] = graph_rate(torch, lambda: plan.eval(P, grad=True, out=out), steps)
     return res
 
@@ -279,7 +287,8 @@ def bench_fitset(gna, W, torch, timer, dev, steps, prec):
     plan = gna.FitSet(problems, model, prec=prec, device=dev)
     P = torch.tensor(params, device=dev)
     plan.autotune(P, reps=3)
-    wall, kmean, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
+    wall, _, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
+    kmean = timer.period
     return {"fits_per_s": len(problems) * steps / wall, "kernel_ms": kmean * 1e3,
             "shape": plan.shape()}
 
@@ -443,6 +452,9 @@ def main():
                      "traffic": measured_traffic(
                          f"scan_kernel<float,true,512,{main_r['shape']['smear_mfma'] + 1},true>"),
                      "kernel_us": main_r["kernel_s"] * 1e6,
+                     "kernel_time": "launch period of the timed back-to-back loop (HIP events "
+                                    "around all steps / steps)",
+                     "event_pair_us": main_r["event_pair_s"] * 1e6,
                      "flops_per_launch": main_r["flops"],
                      "flop_model": f"shared tiles: {FLOPS_SHARED_PER_ITEM} per (quadrature point, "
                                    f"baseline) + {FLOPS_SHARED_PER_POINT_BIN} per (point, bin); "

@@ -20,6 +20,8 @@ The same JSON line also carries, measured in this run:
     batch of 1024 fits (evaluations/s, FP64 and mixed); the single-point
     chains also replayed from a captured HIP graph;
   * mixed_vs_fp64: max errors of the mixed scan against FP64 per output;
+  * transfer_pipeline: P_ee over N = 1e8 energies in host memory, copies in
+    and out serialized against the library's pipelined transfers;
   * roofline of the dominant kernel, cpu_baseline of the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
@@ -317,8 +319,51 @@ def table1_gpu(gna, W, torch, timer, dev):
         t0 = time.perf_counter()
         for _ in range(reps):
             with_transfers()
-        out[str(n)] = {"gpu_compute_s": kmean, "gpu_with_transfers_s": (time.perf_counter() - t0) / reps}
+        serial = (time.perf_counter() - t0) / reps
+        chunk = min(1 << 18, n + (n & 1))
+        piped = lambda: gna.gna_pee_host(E_host, 52.5, W.THETA0, out=P_host, chunk=chunk,
+                                         n_streams=3)
+        for _ in range(10):
+            piped()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            piped()
+        out[str(n)] = {"gpu_compute_s": kmean, "gpu_with_transfers_s": serial,
+                       "gpu_with_transfers_pipelined_s": (time.perf_counter() - t0) / reps}
     return out
+
+
+def transfer_pipeline(gna, W, torch, dev, n=10 ** 8):
+    """P_ee for N = 1e8 energies in pinned host memory, results back to host:
+    serialized (copy in, kernel, copy out) against the library's pipelined
+    transfers (chunks of 2^22 on 3 streams).  GB/s counts the 16 B per element
+    that cross the host link."""
+    E_host = torch.from_numpy(W.config1_energies(n)).pin_memory()
+    P_host = torch.empty(n, dtype=torch.float64).pin_memory()
+    E_dev = torch.empty(n, dtype=torch.float64, device=dev)
+    P_dev = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def serial():
+        E_dev.copy_(E_host, non_blocking=True)
+        gna.gna_pee(E_dev, 52.5, W.THETA0, out=P_dev)
+        P_host.copy_(P_dev, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+
+    ws = None
+    res = {"n": n, "bytes_over_link": 16 * n}
+    for tag, fn in (("serial", serial),
+                    ("pipelined", lambda: gna.gna_pee_host(E_host, 52.5, W.THETA0, out=P_host,
+                                                           chunk=1 << 22, n_streams=3))):
+        fn()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        dt = (time.perf_counter() - t0) / reps
+        res[tag] = {"s": dt, "GBps": 16 * n / dt / 1e9}
+    res["speedup"] = res["serial"]["s"] / res["pipelined"]["s"]
+    del E_host, P_host, E_dev, P_dev
+    return res
 
 
 def table1_cpu(W, threads):
@@ -499,6 +544,8 @@ def main():
                           for p in ("fp64", "mixed")}
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)
+        log("host-memory P_ee, N = 1e8, serialized vs pipelined transfers ...")
+        line["transfer_pipeline"] = transfer_pipeline(gna, W, torch, dev)
     log("cpu baseline (oracle) ...")
     line["cpu_baseline"] = cpu_baseline(W, main_r["pr"])
     if not args.quick:
@@ -510,6 +557,8 @@ def main():
             for tag in ("cpu_1core_s", "cpu_all_cores_s"):
                 t1[n][f"ratio_{tag[:-2]}_over_gpu_with_transfers"] = t1[n][tag] / g["gpu_with_transfers_s"]
                 t1[n][f"ratio_{tag[:-2]}_over_gpu_compute"] = t1[n][tag] / g["gpu_compute_s"]
+                t1[n][f"ratio_{tag[:-2]}_over_gpu_with_pipelined_transfers"] = \
+                    t1[n][tag] / g["gpu_with_transfers_pipelined_s"]
         line["cpu_baseline"]["table1_analogue"] = t1
     print(json.dumps(line, default=lambda o: o if not isinstance(o, np.generic) else o.item()),
           flush=True)

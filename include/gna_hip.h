@@ -115,11 +115,40 @@ int gna_prob(const double* E_dev, int64_t n, int32_t alpha, int32_t beta, int32_
              void* stream);
 
 /*
- * Streaming copy dst_dev[i] = src_dev[i], i < n, with the elementwise
- * kernel's access pattern and grid: the measured HBM-bandwidth reference of
- * the benchmark and the known-size calibration of the memory-traffic
- * counters (not a step of the chain).  Both pointers 16-byte aligned, not
- * overlapping.  Asynchronous.  Errors: GNA_E_INVAL, GNA_E_HIP.
+ * Elementwise P_ee as gna_pee, for energies and results in HOST memory: the
+ * transfer-inclusive path of the paper (energies copied to the device,
+ * evaluated, results copied back: Sec. 4.2 and the first row of Table 1),
+ * pipelined.  The energies go in chunks of `chunk` elements; chunk i uses
+ * buffer slot i % n_streams of the workspace and one of n_streams HIP streams
+ * of the library, so the host-to-device copy, the kernel and the
+ * device-to-host copy of successive chunks overlap.  Results equal gna_pee's
+ * on the same energies bit for bit.
+ *   E_host        host, n doubles [MeV]; pinned (hipHostMalloc) memory lets
+ *                 the copies overlap, pageable memory works but serializes
+ *   P_host        host, n outputs (FP64 doubles or mixed-precision floats)
+ *   workspace_dev device, 256-byte aligned, >= the size from
+ *                 gna_pee_host_workspace_size(chunk, n_streams, prec)
+ *   chunk         even, >= 2 (a few million elements amortize each copy)
+ *   n_streams     1..GNA_PIPE_MAX_STREAMS
+ *   stream        the pipeline starts after the work already queued here
+ * Synchronous: returns when P_host holds every result.  The library's
+ * pipeline streams and event (created at the first call on a device, kept
+ * until the process ends) are shared, so calls are serialized internally.
+ * Errors: GNA_E_INVAL, GNA_E_WORKSPACE, GNA_E_HIP.
+ */
+#define GNA_PIPE_MAX_STREAMS 4
+int gna_pee_host_workspace_size(int64_t chunk, int32_t n_streams, int32_t prec, size_t* bytes);
+int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const double* L_km_host,
+                 const double* wL_host, const double* theta_host, void* P_host, int32_t prec,
+                 void* workspace_dev, size_t workspace_bytes, int64_t chunk, int32_t n_streams,
+                 void* stream);
+
+/*
+ * Streaming copy dst_dev[i] = src_dev[i], i < n: 16-byte non-temporal loads
+ * and stores in the fastest grid shape measured on MI355X; the HBM-bandwidth
+ * reference of the benchmark and the known-size calibration of the
+ * memory-traffic counters (not a step of the chain).  Both pointers 16-byte
+ * aligned, not overlapping.  Asynchronous.  Errors: GNA_E_INVAL, GNA_E_HIP.
  */
 int gna_stream_copy(const double* src_dev, double* dst_dev, int64_t n, void* stream);
 

@@ -156,6 +156,42 @@ def gna_prob(E: torch.Tensor, alpha, beta, L, angles, dm2, wL=None, antineutrino
     return out
 
 
+def gna_pee_host(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Tensor | None = None,
+                 chunk: int = 1 << 22, n_streams: int = 3, device="cuda",
+                 workspace: torch.Tensor | None = None):
+    """gna_pee for energies and results in host memory, through the library's
+    pipelined transfers (chunks of `chunk` energies on `n_streams` streams).
+
+    E: CPU float64 [n] (pinned memory lets copies overlap); returns a CPU
+    tensor (float64 or float32), pinned if E is.  Synchronous.
+    """
+    if not isinstance(E, torch.Tensor) or E.is_cuda or E.dtype != torch.float64 \
+            or not E.is_contiguous():
+        raise TypeError("E must be a contiguous CPU float64 tensor")
+    pr = _prec(prec)
+    L = _f64(np.atleast_1d(L))
+    wLa = None if wL is None else _f64(wL)
+    th = _f64(theta)[:4].copy()
+    odt = torch.float64 if pr == GNA_FP64 else torch.float32
+    n = E.numel()
+    if out is None:
+        out = torch.empty(n, dtype=odt, pin_memory=E.is_pinned())
+    elif out.is_cuda or out.dtype != odt or out.numel() != n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous CPU tensor of E's size and the output dtype")
+    dev = torch.device(device)
+    nbytes = C.c_size_t(0)
+    lib = load()
+    check(lib.gna_pee_host_workspace_size(int(chunk), int(n_streams), pr, C.byref(nbytes)),
+          "gna_pee_host_workspace_size")
+    if workspace is None or workspace.numel() < nbytes.value + 256:
+        workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    ws = workspace.data_ptr() + (-workspace.data_ptr()) % 256
+    check(lib.gna_pee_host(_ptr(E), n, L.size, _dptr(L), _dptr(wLa), _dptr(th), _ptr(out), pr,
+                           C.c_void_p(ws), nbytes.value, int(chunk), int(n_streams),
+                           _stream(dev)), "gna_pee_host")
+    return out
+
+
 def gna_stream_copy(src: torch.Tensor, dst: torch.Tensor):
     """dst <- src with the elementwise kernel's access pattern (bandwidth reference)."""
     _need_cuda(src, "src")

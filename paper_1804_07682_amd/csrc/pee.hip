@@ -9,6 +9,7 @@
 // reciprocal (correctly rounded in FP64 mode, ~2 ulp in mixed mode).
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "gna_internal.h"
 #include "gna_math.h"
@@ -173,35 +174,157 @@ int run_pee(const double* E, int64_t n, int32_t n_L, const double* L, const doub
 }  // namespace
 }  // namespace gna
 
+namespace gna {
+namespace {
+
+// Host-side checks shared by the resident and the host-memory entry points.
+int check_pee_args(const char* who, int64_t n, int32_t n_L, const double* L, const double* th,
+                   int32_t prec) {
+  if (n < 0) return fail(GNA_E_INVAL, "%s: n = %lld < 0", who, (long long)n);
+  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "%s: bad prec %d", who, prec);
+  if (n_L < 1 || n_L > kMaxBaselines)
+    return fail(GNA_E_INVAL, "%s: n_L = %d outside 1..%d", who, n_L, kMaxBaselines);
+  if (!L || !th) return fail(GNA_E_INVAL, "%s: NULL L or theta", who);
+  for (int r = 0; r < n_L; ++r)
+    if (!(L[r] >= 0.0) || !std::isfinite(L[r]))
+      return fail(GNA_E_INVAL, "%s: baseline %d = %g is not a finite value >= 0", who, r, L[r]);
+  const double s12 = th[2], s13 = th[3];
+  if (!(s12 >= 0.0 && s12 <= 1.0 && s13 >= 0.0 && s13 <= 1.0))
+    return fail(GNA_E_INVAL, "%s: s12 = %g, s13 = %g must lie in [0, 1]", who, s12, s13);
+  if (!std::isfinite(th[0]) || !std::isfinite(th[1]))
+    return fail(GNA_E_INVAL, "%s: dm2 not finite", who);
+  return GNA_OK;
+}
+
+int launch_pee(const double* E, int64_t n, int32_t n_L, const double* L, const double* wL,
+               const double* th, void* P, int32_t prec, hipStream_t s) {
+  if (prec == GNA_FP64) return run_pee<double>(E, n, n_L, L, wL, th, P, s);
+  return run_pee<float>(E, n, n_L, L, wL, th, P, s);
+}
+
+// Streams and an event of the transfer pipeline, per device, created at the
+// first call on that device and kept until the process ends.
+constexpr int kMaxDevices = 64;
+struct PipeDev {
+  bool ready = false;
+  hipStream_t st[GNA_PIPE_MAX_STREAMS];
+  hipEvent_t start;
+};
+PipeDev g_pipe[kMaxDevices];
+std::mutex g_pipe_mu;   // guards g_pipe
+std::mutex g_pipe_run;  // one pipelined call at a time (they share streams and the event)
+
+int pipe_resources(PipeDev*& out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(GNA_E_UNSUPPORTED, "device %d", dev);
+  std::lock_guard<std::mutex> lock(g_pipe_mu);
+  PipeDev& d = g_pipe[dev];
+  if (!d.ready) {
+    for (int k = 0; k < GNA_PIPE_MAX_STREAMS; ++k)
+      if ((rc = check_hip(hipStreamCreateWithFlags(&d.st[k], hipStreamNonBlocking),
+                          "hipStreamCreateWithFlags")))
+        return rc;
+    if ((rc = check_hip(hipEventCreateWithFlags(&d.start, hipEventDisableTiming),
+                        "hipEventCreateWithFlags")))
+      return rc;
+    d.ready = true;
+  }
+  out = &d;
+  return GNA_OK;
+}
+
+size_t pipe_slot_bytes(int64_t chunk, int32_t prec) {
+  const size_t osz = prec == GNA_FP64 ? 8 : 4;
+  return align_up((size_t)chunk * 8, 256) + align_up((size_t)chunk * osz, 256);
+}
+
+}  // namespace
+}  // namespace gna
+
 extern "C" int gna_pee(const double* E_dev, int64_t n, int32_t n_L, const double* L_km_host,
                        const double* wL_host, const double* theta_host, void* P_dev,
                        int32_t prec, void* stream) {
   using namespace gna;
   clear_error();
-  if (n < 0) return fail(GNA_E_INVAL, "gna_pee: n = %lld < 0", (long long)n);
-  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "gna_pee: bad prec %d", prec);
-  if (n_L < 1 || n_L > kMaxBaselines)
-    return fail(GNA_E_INVAL, "gna_pee: n_L = %d outside 1..%d", n_L, kMaxBaselines);
-  if (!L_km_host || !theta_host) return fail(GNA_E_INVAL, "gna_pee: NULL L or theta");
-  for (int r = 0; r < n_L; ++r)
-    if (!(L_km_host[r] >= 0.0) || !std::isfinite(L_km_host[r]))
-      return fail(GNA_E_INVAL, "gna_pee: baseline %d = %g is not a finite value >= 0", r,
-                  L_km_host[r]);
-  const double s12 = theta_host[2], s13 = theta_host[3];
-  if (!(s12 >= 0.0 && s12 <= 1.0 && s13 >= 0.0 && s13 <= 1.0))
-    return fail(GNA_E_INVAL, "gna_pee: s12 = %g, s13 = %g must lie in [0, 1]", s12, s13);
-  if (!std::isfinite(theta_host[0]) || !std::isfinite(theta_host[1]))
-    return fail(GNA_E_INVAL, "gna_pee: dm2 not finite");
+  int rc = check_pee_args("gna_pee", n, n_L, L_km_host, theta_host, prec);
+  if (rc) return rc;
   if (n == 0) return GNA_OK;
   if (!E_dev || !P_dev) return fail(GNA_E_INVAL, "gna_pee: NULL device pointer");
   if (((uintptr_t)E_dev & 15) != 0) return fail(GNA_E_INVAL, "gna_pee: E_dev not 16-byte aligned");
   const uintptr_t palign = (prec == GNA_FP64) ? 15 : 7;
   if (((uintptr_t)P_dev & palign) != 0)
     return fail(GNA_E_INVAL, "gna_pee: P_dev not %d-byte aligned", (int)palign + 1);
-  hipStream_t s = (hipStream_t)stream;
-  if (prec == GNA_FP64)
-    return run_pee<double>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
-  return run_pee<float>(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, s);
+  return launch_pee(E_dev, n, n_L, L_km_host, wL_host, theta_host, P_dev, prec,
+                    (hipStream_t)stream);
+}
+
+extern "C" int gna_pee_host_workspace_size(int64_t chunk, int32_t n_streams, int32_t prec,
+                                           size_t* bytes) {
+  using namespace gna;
+  clear_error();
+  if (!bytes) return fail(GNA_E_INVAL, "gna_pee_host_workspace_size: NULL bytes");
+  if (chunk < 2 || (chunk & 1)) return fail(GNA_E_INVAL, "chunk = %lld must be even and >= 2", (long long)chunk);
+  if (n_streams < 1 || n_streams > GNA_PIPE_MAX_STREAMS)
+    return fail(GNA_E_INVAL, "n_streams = %d outside 1..%d", n_streams, GNA_PIPE_MAX_STREAMS);
+  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "bad prec %d", prec);
+  *bytes = (size_t)n_streams * pipe_slot_bytes(chunk, prec);
+  return GNA_OK;
+}
+
+extern "C" int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const double* L_km_host,
+                            const double* wL_host, const double* theta_host, void* P_host,
+                            int32_t prec, void* workspace_dev, size_t workspace_bytes,
+                            int64_t chunk, int32_t n_streams, void* stream) {
+  using namespace gna;
+  clear_error();
+  int rc = check_pee_args("gna_pee_host", n, n_L, L_km_host, theta_host, prec);
+  if (rc) return rc;
+  size_t need = 0;
+  if ((rc = gna_pee_host_workspace_size(chunk, n_streams, prec, &need))) return rc;
+  if (n == 0) return GNA_OK;
+  if (!E_host || !P_host) return fail(GNA_E_INVAL, "gna_pee_host: NULL host pointer");
+  if (!workspace_dev || ((uintptr_t)workspace_dev & 255) != 0)
+    return fail(GNA_E_INVAL, "gna_pee_host: workspace NULL or not 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(GNA_E_WORKSPACE, "gna_pee_host: workspace %zu bytes, needs %zu", workspace_bytes,
+                need);
+  std::lock_guard<std::mutex> running(g_pipe_run);
+  PipeDev* pd = nullptr;
+  if ((rc = pipe_resources(pd))) return rc;
+  // Start after the work already queued on the caller's stream.
+  if ((rc = check_hip(hipEventRecord(pd->start, (hipStream_t)stream), "hipEventRecord")))
+    return rc;
+  for (int k = 0; k < n_streams; ++k)
+    if ((rc = check_hip(hipStreamWaitEvent(pd->st[k], pd->start, 0), "hipStreamWaitEvent")))
+      return rc;
+  const size_t osz = prec == GNA_FP64 ? 8 : 4;
+  const size_t slot = pipe_slot_bytes(chunk, prec);
+  unsigned char* ws = (unsigned char*)workspace_dev;
+  // Chunk i on stream i % n_streams: a slot's buffers are reused only after
+  // the same (in-order) stream has copied its previous chunk back.
+  for (int64_t i = 0, off = 0; off < n; ++i, off += chunk) {
+    const int k = (int)(i % n_streams);
+    const int64_t m = std::min(chunk, n - off);
+    double* E_dev = (double*)(ws + k * slot);
+    void* P_dev = ws + k * slot + align_up((size_t)chunk * 8, 256);
+    hipStream_t s = pd->st[k];
+    if ((rc = check_hip(hipMemcpyAsync(E_dev, E_host + off, (size_t)m * 8, hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync (energies)")))
+      break;
+    if ((rc = launch_pee(E_dev, m, n_L, L_km_host, wL_host, theta_host, P_dev, prec, s))) break;
+    if ((rc = check_hip(hipMemcpyAsync((unsigned char*)P_host + (size_t)off * osz, P_dev,
+                                       (size_t)m * osz, hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync (probabilities)")))
+      break;
+  }
+  // Drain every stream (also after an error, so no copy is left in flight).
+  for (int k = 0; k < n_streams; ++k) {
+    const int r2 = check_hip(hipStreamSynchronize(pd->st[k]), "hipStreamSynchronize");
+    if (!rc) rc = r2;
+  }
+  return rc;
 }
 
 // ---------------------------------------------------------------------------

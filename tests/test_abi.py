@@ -130,3 +130,32 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIBPATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_pee_host_sizing_and_validation(lib):
+    """Workspace sizing and argument checks of the transfer pipeline run on the
+    host, before any HIP call."""
+    nb = C.c_size_t(0)
+    assert lib.gna_pee_host_workspace_size(4096, 2, 0, C.byref(nb)) == 0
+    assert nb.value == 2 * (4096 * 8 + 4096 * 8)
+    assert lib.gna_pee_host_workspace_size(4096, 3, 1, C.byref(nb)) == 0
+    assert nb.value == 3 * (4096 * 8 + 4096 * 4)
+    for chunk, ns, prec in ((4095, 1, 0), (0, 1, 0), (4096, 0, 0), (4096, 5, 0), (4096, 1, 7)):
+        assert lib.gna_pee_host_workspace_size(chunk, ns, prec, C.byref(nb)) == -1
+    L = np.array([52.5])
+    th = np.array([7.5e-5, 2.5e-3, 0.3, 0.02])
+    dp = C.POINTER(C.c_double)
+    E = np.ones(8)
+    P = np.zeros(8)
+
+    def call(n=8, ws=C.c_void_p(256), ws_bytes=1 << 20, chunk=4096, ns=2, Eh=E, th_=th):
+        return lib.gna_pee_host(Eh.ctypes.data if Eh is not None else None, n, 1,
+                                L.ctypes.data_as(dp), None, th_.ctypes.data_as(dp),
+                                P.ctypes.data, 0, ws, ws_bytes, chunk, ns, None)
+
+    assert call(n=0) == 0                      # nothing to do, no HIP call
+    assert call(Eh=None) == -1                 # NULL host pointer
+    assert call(ws=C.c_void_p(16)) == -1       # misaligned workspace
+    assert call(ws_bytes=100) == -4            # workspace too small
+    assert call(chunk=3) == -1                 # odd chunk
+    assert call(th_=np.array([7.5e-5, 2.5e-3, 1.3, 0.02])) == -1  # s12 outside [0, 1]

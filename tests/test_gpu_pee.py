@@ -112,3 +112,45 @@ def test_stream_copy():
         gna.gna_stream_copy(a, b)
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n_streams", [1, 2, 3])
+def test_pee_host_pipeline_matches_resident(prec, n_streams):
+    """Energies in host memory through the pipelined transfers give the same
+    bits as gna_pee on the same energies resident on the device."""
+    import paper_1804_07682_amd as gna
+    chunk = 4096
+    for n in (1, 3, chunk - 1, chunk, chunk + 1, 5 * chunk + 7):
+        for pinned in (True, False):
+            E = torch.from_numpy(W.config1_energies(n))
+            if pinned:
+                E = E.pin_memory()
+            got = gna.gna_pee_host(E, 52.5, TH, prec=prec, chunk=chunk, n_streams=n_streams)
+            ref = gna.gna_pee(E.to(DEV), 52.5, TH, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(got, ref.cpu()), (n, pinned)
+
+
+def test_pee_host_pipeline_several_baselines_and_errors():
+    import paper_1804_07682_amd as gna
+    E = torch.from_numpy(W.config1_energies(100_001)).pin_memory()
+    L = np.linspace(50, 55, 8)
+    got = gna.gna_pee_host(E, L, TH, chunk=16384, n_streams=2)
+    ref = oracle.pee(E.numpy(), L, TH, n_threads=8)
+    assert np.max(rel_err(got.numpy(), ref)) <= FP64_RTOL
+    assert gna.gna_pee_host(torch.empty(0, dtype=torch.float64), 52.5, TH).numel() == 0
+    with pytest.raises(gna.GnaError):
+        gna.gna_pee_host(E, 52.5, TH, chunk=4097)
+    small = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    import paper_1804_07682_amd._lib as L_
+    import ctypes as C
+    out = torch.empty(E.numel(), dtype=torch.float64)
+    th = np.asarray(TH[:4], dtype=np.float64)
+    Ls = np.array([52.5])
+    dp = C.POINTER(C.c_double)
+    ws = small.data_ptr() + (-small.data_ptr()) % 256
+    rc = L_.load().gna_pee_host(E.data_ptr(), E.numel(), 1, Ls.ctypes.data_as(dp), None,
+                                th.ctypes.data_as(dp), out.data_ptr(), 0, C.c_void_p(ws), 512,
+                                4096, 2, None)
+    assert rc == L_.GNA_E_WORKSPACE

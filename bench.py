@@ -22,6 +22,9 @@ The same JSON line also carries, measured in this run:
   * mixed_vs_fp64: max errors of the mixed scan against FP64 per output;
   * transfer_pipeline: P_ee over N = 1e8 energies in host memory, copies in
     and out serialized against the library's pipelined transfers;
+  * graph: the transformation graph of the config-0 chain read back after a
+    change of dm2_31 (full recompute) or of the normalisation only (lazy:
+    two nodes), beside the fused chain;
   * roofline of the dominant kernel, cpu_baseline of the oracle.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
@@ -366,6 +369,49 @@ def transfer_pipeline(gna, W, torch, dev, n=10 ** 8):
     return res
 
 
+def graph_lazy(gna, W, torch, dev, reps=200):
+    """Transformation graph of the config-0 chain (points -> P_ee -> flux product
+    -> bin sums -> smearing -> norm -> chi^2), read back after changing dm2_31
+    (every node after the points recomputed) or only the normalisation (two
+    nodes recomputed), against the fused chain for the same evaluation."""
+    model = W.model()
+    pr = W.config0()
+    tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
+    nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
+                  pred=True)["pred"].cpu().numpy()[0]
+    pr["data"] = W.poisson_counts(nu, W.SEED)
+    g = gna.Graph(dev)
+    v = [g.variable(nm, W.THETA0[i]) for i, nm in enumerate(("dm21", "dm31", "s12", "s13", "norm"))]
+    pts = g.points(pr, model)
+    osc = g.oscprob(pts, 52.5, v[0], v[1], v[2], v[3])
+    chi2 = g.chi2(g.scale(g.smear(g.integrate(g.product(g.flux(pts), osc), pts), pts), v[4]), pts)
+    g.bind()
+    res = {}
+    for tag, var, base in (("dm31_changed", v[1], W.THETA0[1]), ("norm_changed", v[4], 1.0)):
+        g.read(chi2)
+        t0 = time.perf_counter()
+        for i in range(reps):
+            g.set(var, base * (1.0 + 1e-6 * (i % 2 + 1)))
+            g.read(chi2)
+        res[f"{tag}_us"] = (time.perf_counter() - t0) / reps * 1e6
+    plan = gna.Chain(pr, model, max_batch=1, device=dev, opts={"smear_mfma": 0})
+    P = torch.tensor(W.THETA0, device=dev).reshape(1, 5)
+    out = {"chi2": torch.empty(1, dtype=torch.float64, device=dev)}
+    host = torch.empty(1, dtype=torch.float64).pin_memory()
+    def fused():
+        plan.eval(P, grad=False, out=out)
+        host.copy_(out["chi2"], non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+    fused()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fused()
+    res["fused_chain_us"] = (time.perf_counter() - t0) / reps * 1e6
+    res["note"] = "chi^2 read back to the host each time (one synchronising copy per evaluation)"
+    g.close()
+    return res
+
+
 def table1_cpu(W, threads):
     import oracle
     res = {}
@@ -544,6 +590,8 @@ def main():
                           for p in ("fp64", "mixed")}
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)
+        log("transformation graph, lazy evaluation ...")
+        line["graph"] = graph_lazy(gna, W, torch, dev)
         log("host-memory P_ee, N = 1e8, serialized vs pipelined transfers ...")
         line["transfer_pipeline"] = transfer_pipeline(gna, W, torch, dev)
     log("cpu baseline (oracle) ...")

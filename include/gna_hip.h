@@ -333,6 +333,77 @@ int gna_gl_nodes(int32_t order, double* t_dev, double* w_dev, void* stream);
 int gna_plan_tables(const gna_plan* plan, int32_t index, double* E_dev, double* f_dev,
                     double* R_dev, void* stream);
 
+/* ---- transformation graph (Sec. 2, Fig. 2-6) ------------------------------
+ * A graph of vector-in / vector-out transformations over the kernels above,
+ * in the paper's two stages.  Configuration: create variables (scalars) and
+ * nodes, each owning one FP64 output vector; a node's inputs are read-only.
+ * Then gna_graph_workspace_size / gna_graph_bind place every output, and the
+ * configuration tables of each geometry, in one caller-allocated device
+ * workspace and compute those tables.  Computation: gna_graph_set changes a
+ * variable and taints every node that depends on it, directly or through its
+ * inputs; gna_graph_eval / gna_graph_read recompute only tainted nodes, inputs
+ * first (lazy evaluation), and a node is computed at most once between
+ * changes of what it depends on.  Reading any node's output, intermediate or
+ * final, costs one device-to-host copy (Sec. 4.2).  The graph runs unfused
+ * kernels, one per node, in FP64; the fused chain entry points above are the
+ * fast path for the same chain.
+ *
+ * Node ids are dense from 0 in creation order; variable ids likewise (their
+ * own numbering).  Every function returns GNA_OK or an error code (message in
+ * gna_last_error_message); creation functions fail after gna_graph_bind, and
+ * computation functions before it.  A graph is used by one host thread at a
+ * time.
+ */
+typedef struct gna_graph gna_graph;
+int gna_graph_create(gna_graph** graph_out);
+int gna_graph_destroy(gna_graph* graph);
+/* A scalar variable (dm2_21, sin^2 theta_13, a normalisation, ...). */
+int gna_graph_variable(gna_graph* graph, const char* name, double value, int32_t* var_out);
+/* Geometry node: quadrature energies E_k [n_bins * gl_order * n_sub] of a
+ * problem (the problem's edges, quadrature and data are copied; its
+ * baselines are not used by the graph).  The geometry also carries the flux
+ * factors f_k, the smearing matrix R and the data of the problem. */
+int gna_graph_points(gna_graph* graph, const gna_model* model, const gna_problem* problem,
+                     int32_t* node_out);
+/* f_k = N0 S(E_k) sigma(E_k) w_k of a geometry: a configuration table, never tainted. */
+int gna_graph_flux(gna_graph* graph, int32_t points, int32_t* node_out);
+/* P_ee(E; L) over a node's energies, Sec. 4.1, with four variables
+ * (dm2_21, dm2_31, sin^2 th12, sin^2 th13). */
+int gna_graph_oscprob(gna_graph* graph, int32_t energies, double L_km, const int32_t vars[4],
+                      int32_t* node_out);
+/* sum_i w_i x_i over n_inputs nodes of equal length (1..64 inputs). */
+int gna_graph_sum(gna_graph* graph, int32_t n_inputs, const int32_t* inputs,
+                  const double* weights, int32_t* node_out);
+/* Elementwise product of two nodes of equal length. */
+int gna_graph_product(gna_graph* graph, int32_t a, int32_t b, int32_t* node_out);
+/* Bin sums of a per-quadrature-point node of a geometry: [n_bins]. */
+int gna_graph_integrate(gna_graph* graph, int32_t x, int32_t points, int32_t* node_out);
+/* R x of a per-bin node with the geometry's smearing matrix: [n_bins]. */
+int gna_graph_smear(gna_graph* graph, int32_t x, int32_t points, int32_t* node_out);
+/* v x with a variable v. */
+int gna_graph_scale(gna_graph* graph, int32_t x, int32_t var, int32_t* node_out);
+/* Baker-Cousins Poisson chi^2 of a per-bin prediction against the geometry's
+ * data: [1]. */
+int gna_graph_chi2(gna_graph* graph, int32_t nu, int32_t points, int32_t* node_out);
+/* Device bytes gna_graph_bind needs (outputs and configuration tables). */
+int gna_graph_workspace_size(const gna_graph* graph, size_t* bytes);
+/* Place outputs in workspace_dev (256-byte aligned, >= the size above) and
+ * compute the configuration tables on `stream`.  Synchronous.  The graph
+ * keeps the workspace until it is destroyed. */
+int gna_graph_bind(gna_graph* graph, void* workspace_dev, size_t workspace_bytes, void* stream);
+/* Change a variable: taints its dependents (no computation). */
+int gna_graph_set(gna_graph* graph, int32_t var, double value);
+/* Compute `node` and whatever it needs that is tainted, on `stream`
+ * (asynchronous), and return its output's device address and length. */
+int gna_graph_eval(gna_graph* graph, int32_t node, void* stream, const double** out_dev,
+                   int64_t* n_out);
+/* gna_graph_eval, then copy the output to host_out[n] (n = its length).
+ * Synchronous. */
+int gna_graph_read(gna_graph* graph, int32_t node, double* host_out, int64_t n, void* stream);
+/* Output length of a node, and how many times it has been computed. */
+int gna_graph_node_info(const gna_graph* graph, int32_t node, int64_t* n_out,
+                        int64_t* evaluations);
+
 #ifdef __cplusplus
 }
 #endif

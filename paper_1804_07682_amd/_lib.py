@@ -53,7 +53,13 @@ class Plan(C.Structure):
     pass
 
 
+class Graph(C.Structure):
+    pass
+
+
 _PlanP = C.POINTER(Plan)
+_GraphP = C.POINTER(Graph)
+_i32p = C.POINTER(C.c_int32)
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -89,6 +95,26 @@ SIGNATURES = {
     "gna_plan_destroy": (C.c_int, [_PlanP]),
     "gna_gl_nodes": (C.c_int, [C.c_int32, _vp, _vp, _vp]),
     "gna_plan_tables": (C.c_int, [_PlanP, C.c_int32, _vp, _vp, _vp, _vp]),
+    "gna_graph_create": (C.c_int, [C.POINTER(_GraphP)]),
+    "gna_graph_destroy": (C.c_int, [_GraphP]),
+    "gna_graph_variable": (C.c_int, [_GraphP, C.c_char_p, C.c_double, _i32p]),
+    "gna_graph_points": (C.c_int, [_GraphP, C.POINTER(Model), C.POINTER(Problem), _i32p]),
+    "gna_graph_flux": (C.c_int, [_GraphP, C.c_int32, _i32p]),
+    "gna_graph_oscprob": (C.c_int, [_GraphP, C.c_int32, C.c_double, _i32p, _i32p]),
+    "gna_graph_sum": (C.c_int, [_GraphP, C.c_int32, _i32p, _dp, _i32p]),
+    "gna_graph_product": (C.c_int, [_GraphP, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_integrate": (C.c_int, [_GraphP, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_smear": (C.c_int, [_GraphP, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_scale": (C.c_int, [_GraphP, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_chi2": (C.c_int, [_GraphP, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_workspace_size": (C.c_int, [_GraphP, C.POINTER(C.c_size_t)]),
+    "gna_graph_bind": (C.c_int, [_GraphP, _vp, C.c_size_t, _vp]),
+    "gna_graph_set": (C.c_int, [_GraphP, C.c_int32, C.c_double]),
+    "gna_graph_eval": (C.c_int, [_GraphP, C.c_int32, _vp, C.POINTER(_dp),
+                                 C.POINTER(C.c_int64)]),
+    "gna_graph_read": (C.c_int, [_GraphP, C.c_int32, _dp, C.c_int64, _vp]),
+    "gna_graph_node_info": (C.c_int, [_GraphP, C.c_int32, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]),
 }
 
 _lib = None

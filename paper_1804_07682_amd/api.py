@@ -422,3 +422,121 @@ class Chi2Fn(torch.autograd.Function):
 
 def chi2(params: torch.Tensor, plan: Chain) -> torch.Tensor:
     return Chi2Fn.apply(params, plan)
+
+
+class Graph:
+    """Transformation graph over the library's kernels (``gna_graph_*``).
+
+    Configuration: ``variable`` / ``points`` / ``flux`` / ``oscprob`` / ``sum``
+    / ``product`` / ``integrate`` / ``smear`` / ``scale`` / ``chi2`` return
+    ids; ``bind()`` places every output in one device workspace (allocated
+    here through torch) and computes the configuration tables.  Computation:
+    ``set(var, value)`` taints the dependents of a variable, ``read(node)``
+    recomputes only what is tainted and returns the node's output as a numpy
+    array, ``eval(node)`` does the same but returns the output as a device
+    tensor view (valid until the next evaluation that recomputes it).
+    """
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self._g = _lib._GraphP()
+        check(load().gna_graph_create(C.byref(self._g)), "gna_graph_create")
+        self._keep = []
+        self.workspace = None
+
+    def _id(self, fn, *args):
+        out = C.c_int32(-1)
+        check(fn(self._g, *args, C.byref(out)), fn.__name__)
+        return out.value
+
+    def variable(self, name: str, value: float) -> int:
+        return self._id(load().gna_graph_variable, name.encode(), float(value))
+
+    def points(self, problem: dict, model: dict) -> int:
+        m = make_model(model)
+        p = make_problem(problem, self._keep)
+        return self._id(load().gna_graph_points, C.byref(m), C.byref(p))
+
+    def flux(self, points: int) -> int:
+        return self._id(load().gna_graph_flux, points)
+
+    def oscprob(self, energies: int, L_km: float, dm21: int, dm31: int, s12: int, s13: int) -> int:
+        v = (C.c_int32 * 4)(dm21, dm31, s12, s13)
+        return self._id(load().gna_graph_oscprob, energies, float(L_km), v)
+
+    def sum(self, inputs, weights) -> int:
+        ids = (C.c_int32 * len(inputs))(*inputs)
+        w = _f64(weights)
+        self._keep.append(w)
+        return self._id(load().gna_graph_sum, len(inputs), ids, _dptr(w))
+
+    def product(self, a: int, b: int) -> int:
+        return self._id(load().gna_graph_product, a, b)
+
+    def integrate(self, x: int, points: int) -> int:
+        return self._id(load().gna_graph_integrate, x, points)
+
+    def smear(self, x: int, points: int) -> int:
+        return self._id(load().gna_graph_smear, x, points)
+
+    def scale(self, x: int, var: int) -> int:
+        return self._id(load().gna_graph_scale, x, var)
+
+    def chi2(self, nu: int, points: int) -> int:
+        return self._id(load().gna_graph_chi2, nu, points)
+
+    def bind(self):
+        nbytes = C.c_size_t(0)
+        check(load().gna_graph_workspace_size(self._g, C.byref(nbytes)), "gna_graph_workspace_size")
+        raw = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self.workspace = raw
+        check(load().gna_graph_bind(self._g, C.c_void_p(raw.data_ptr() + off), nbytes.value,
+                                    _stream(self.device)), "gna_graph_bind")
+        return self
+
+    def set(self, var: int, value: float):
+        check(load().gna_graph_set(self._g, var, float(value)), "gna_graph_set")
+
+    def info(self, node: int):
+        n = C.c_int64(0)
+        ev = C.c_int64(0)
+        check(load().gna_graph_node_info(self._g, node, C.byref(n), C.byref(ev)),
+              "gna_graph_node_info")
+        return {"n": n.value, "evaluations": ev.value}
+
+    def _graph_stream(self):
+        # Unbound graphs are refused by the library before any HIP call.
+        return None if self.workspace is None else _stream(self.device)
+
+    def read(self, node: int) -> np.ndarray:
+        n = self.info(node)["n"]
+        out = np.empty(n, dtype=np.float64)
+        check(load().gna_graph_read(self._g, node, _dptr(out), n, self._graph_stream()),
+              "gna_graph_read")
+        return out
+
+    def eval(self, node: int) -> torch.Tensor:
+        ptr = _lib._dp()
+        n = C.c_int64(0)
+        check(load().gna_graph_eval(self._g, node, self._graph_stream(), C.byref(ptr),
+                                    C.byref(n)), "gna_graph_eval")
+        addr = C.cast(ptr, C.c_void_p).value
+        base = self.workspace.data_ptr()
+        if addr is None or not (base <= addr < base + self.workspace.numel()):
+            # configuration tables live in the bound workspace too; anything
+            # else would be a library error
+            raise GnaError(_lib.GNA_E_INVAL, "graph output outside its workspace")
+        off = addr - base
+        return self.workspace[off:off + 8 * n.value].view(torch.float64)
+
+    def close(self):
+        if self._g:
+            load().gna_graph_destroy(self._g)
+            self._g = _lib._GraphP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

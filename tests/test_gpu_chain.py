@@ -227,3 +227,18 @@ def test_chi2_with_data_far_from_prediction(mfma):
     got = _eval(_plan(pr, B=P.shape[0], smear_mfma=mfma), P)
     assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL
     assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= FP64_RTOL
+
+
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_autograd_gradcheck_mini_config(mfma):
+    """torch.autograd.gradcheck of the chi^2 function (adjoint backward against
+    central differences) on a mini-config: 8 bins, GL order 3, 2 baselines.
+    The parameters enter as theta0 (1 + u), so one step eps suits all five."""
+    import paper_1804_07682_amd as gna
+    pr = with_data(W.problem(W.uniform_edges(8), 3, [52.5, 700.0]), MODEL, 3)
+    plan = gna.Chain(pr, MODEL, max_batch=2, opts={"smear_mfma": mfma}, device=DEV)
+    th0 = torch.tensor(np.vstack([W.THETA0, np.array(W.THETA0) * 1.03]), dtype=torch.float64,
+                       device=DEV)
+    u = torch.zeros_like(th0, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda u: gna.chi2(th0 * (1 + u), plan), (u,), eps=1e-6,
+                                    atol=1e-6, rtol=1e-4)

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GNA_ABI_VERSION 3
+#define GNA_ABI_VERSION 4
 
 /* ---- status codes -------------------------------------------------------- */
 #define GNA_OK 0
@@ -221,6 +221,13 @@ typedef struct gna_problem {
  *                  rounding, so a point's last bits may depend on its tile
  *                  neighbours.  1: every point evaluates its own phases, and
  *                  its result does not depend on the rest of the batch.
+ *   split_tail     (fitset plans only) 0: automatic; 1: each fit's tail
+ *                  (smearing, chi^2, adjoint) runs in the work-group that
+ *                  finishes the fit's last tile; 2: the point pass only
+ *                  stores bin sums, and three more launches run the tails of
+ *                  all fits with one wavefront per 64-row slice (forward) and
+ *                  per 64-column block (adjoint), then add each fit's
+ *                  partials in a fixed order.
  */
 typedef struct gna_launch_opts {
   int32_t threads;
@@ -229,6 +236,7 @@ typedef struct gna_launch_opts {
   int32_t persistent;
   int32_t smear_mfma;
   int32_t no_shared_phases;
+  int32_t split_tail;
 } gna_launch_opts;
 
 typedef struct gna_plan gna_plan;
@@ -296,12 +304,13 @@ int gna_fitset_eval(gna_plan* plan, const double* params_dev, double* chi2_dev,
  * Returns GNA_E_DOMAIN if any bit was set, else GNA_OK (or GNA_E_HIP).
  */
 int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
-/* Launch shape in use: writes 6 ints (threads, lanes_per_bin, chunks,
- * persistent, smear_mfma, shared_phases) and the number of tiles of one
- * evaluation.  shared_phases is 1 when the MFMA kernel lets tiles with common
- * (dm2_21, dm2_31) share their phases: the plan allows it (no_shared_phases
- * = 0) and the shape asks for it (the autotuner tries both). */
-int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_t* n_tiles);
+/* Launch shape in use: writes 7 ints (threads, lanes_per_bin, chunks,
+ * persistent, smear_mfma, shared_phases, split_tail) and the number of tiles
+ * of one evaluation.  shared_phases is 1 when the MFMA kernel lets tiles with
+ * common (dm2_21, dm2_31) share their phases: the plan allows it
+ * (no_shared_phases = 0) and the shape asks for it (the autotuner tries
+ * both).  split_tail is 1 when a fitset runs its tails in separate launches. */
+int gna_plan_shape(const gna_plan* plan, int32_t shape_out[7], int64_t* n_tiles);
 /*
  * Project-written autotuner: times each candidate launch shape of this plan
  * on `stream` with HIP events (median of `reps` evaluations at params_dev,
@@ -313,7 +322,7 @@ int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_t* n_tiles)
  */
 int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32_t B, double* chi2_dev,
                       double* grad_dev, int32_t reps, const char* cache_path, void* stream,
-                      int32_t shape_out[6]);
+                      int32_t shape_out[7]);
 /* Frees the host-side plan (the caller still owns the workspace). */
 int gna_plan_destroy(gna_plan* plan);
 

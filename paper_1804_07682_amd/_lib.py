@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libgna_hip.so")
 
-ABI_VERSION = 3  # the layout of the structs below
+ABI_VERSION = 4  # the layout of the structs below
 GNA_OK = 0
 GNA_E_INVAL = -1
 GNA_E_DOMAIN = -2
@@ -46,7 +46,8 @@ class Problem(C.Structure):
 class LaunchOpts(C.Structure):
     _fields_ = [("threads", C.c_int32), ("lanes_per_bin", C.c_int32), ("chunks", C.c_int32),
                 ("persistent", C.c_int32), ("smear_mfma", C.c_int32),
-                ("no_shared_phases", C.c_int32)]
+                ("no_shared_phases", C.c_int32),
+                ("split_tail", C.c_int32)]
 
 
 class Plan(C.Structure):

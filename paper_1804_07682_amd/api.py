@@ -102,6 +102,7 @@ def make_opts(opts) -> LaunchOpts | None:
     o.persistent = int(opts.get("persistent", 0))
     o.smear_mfma = int(opts.get("smear_mfma", -1))
     o.no_shared_phases = int(bool(opts.get("no_shared_phases", 0)))
+    o.split_tail = int(opts.get("split_tail", 0))
     return o
 
 
@@ -237,11 +238,11 @@ class _PlanBase:
         return word.value
 
     def shape(self):
-        s = (C.c_int32 * 6)()
+        s = (C.c_int32 * 7)()
         n = C.c_int64(0)
         check(load().gna_plan_shape(self._plan, s, C.byref(n)), "gna_plan_shape")
         keys = ("threads", "lanes_per_bin", "chunks", "persistent", "smear_mfma",
-                "shared_phases")
+                "shared_phases", "split_tail")
         d = dict(zip(keys, list(s)))
         d["n_tiles"] = n.value
         return d
@@ -265,7 +266,7 @@ class _PlanBase:
         B = params.shape[0]
         chi2 = torch.empty(B, dtype=torch.float64, device=self.device)
         grad = torch.empty((B, 5), dtype=torch.float64, device=self.device)
-        s = (C.c_int32 * 6)()
+        s = (C.c_int32 * 7)()
         path = None if cache_path is None else str(cache_path).encode()
         check(load().gna_plan_autotune(self._plan, _ptr(params), B, _ptr(chi2), _ptr(grad), reps,
                                        path, _stream(self.device), s), "gna_plan_autotune")

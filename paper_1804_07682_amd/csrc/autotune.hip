@@ -49,16 +49,19 @@ bool cache_lookup(const char* path, const std::string& key, Shape& sh) {
   if (at == std::string::npos) return false;
   const size_t lb = text.find('[', at);
   if (lb == std::string::npos) return false;
-  int v[6] = {0, 0, 0, 0, 0, 1};
-  const int got = std::sscanf(text.c_str() + lb, "[%d, %d, %d, %d, %d, %d]", &v[0], &v[1], &v[2],
-                              &v[3], &v[4], &v[5]);
-  if (got < 5) return false;  // entries without the sixth value predate phase sharing
+  int v[7] = {0, 0, 0, 0, 0, 1, 0};
+  const int got = std::sscanf(text.c_str() + lb, "[%d, %d, %d, %d, %d, %d, %d]", &v[0], &v[1], &v[2],
+                              &v[3], &v[4], &v[5], &v[6]);
+  // Entries without the sixth value predate phase sharing, without the
+  // seventh the split tail.
+  if (got < 5) return false;
   sh.threads = v[0];
   sh.G = v[1];
   sh.C = v[2];
   sh.persistent = v[3];
   sh.mfma = v[4];
   sh.share = v[5];
+  sh.split = v[6];
   return true;
 }
 
@@ -83,8 +86,8 @@ void cache_store(const char* path, const std::string& key, const Shape& sh) {
     }
   }
   char val[96];
-  std::snprintf(val, sizeof(val), "[%d, %d, %d, %d, %d, %d]", sh.threads, sh.G, sh.C,
-                sh.persistent, sh.mfma, sh.share);
+  std::snprintf(val, sizeof(val), "[%d, %d, %d, %d, %d, %d, %d]", sh.threads, sh.G, sh.C,
+                sh.persistent, sh.mfma, sh.share, sh.split);
   bool found = false;
   for (auto& e : entries)
     if (e.first == key) {
@@ -117,7 +120,7 @@ using namespace gna;
 
 extern "C" int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32_t B,
                                  double* chi2_dev, double* grad_dev, int32_t reps,
-                                 const char* cache_path, void* stream, int32_t shape_out[6]) {
+                                 const char* cache_path, void* stream, int32_t shape_out[7]) {
   clear_error();
   if (!plan || !plan->ws) return fail(GNA_E_INVAL, "plan is NULL");
   if (!params_dev || !chi2_dev) return fail(GNA_E_INVAL, "params or chi2 NULL");

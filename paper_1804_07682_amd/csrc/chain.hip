@@ -37,6 +37,11 @@ __device__ __forceinline__ float rfma<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
+// Band loads issued back to back in the smearing loops of the tail (32
+// VGPRs of operands either way).
+template <class R>
+constexpr int kTailBatch = sizeof(R) == 8 ? 8 : 16;
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -107,9 +112,8 @@ __device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict_
     const bool vB = sB >= 0 && sB < ns, vA = sA >= 0 && sA < ns;
     const SliceDev zB = vB ? slices[sB] : SliceDev{0, 0, 0};
     const SliceDev zA = vA ? slices[sA] : SliceDev{0, 0, 0};
-#pragma unroll 4
-    for (; d < dend; ++d) {
-      const int r = d - m * kSlice;
+    auto term = [&](int dd, R& rv, R& g) {
+      const int r = dd - m * kSlice;
       const bool useB = lane >= r;
       const int s = useB ? sB : sA;
       const int dlo = useB ? zB.dlo : zA.dlo;
@@ -117,16 +121,32 @@ __device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict_
       const int64_t off = useB ? zB.off : zA.off;
       const int li = useB ? lane - r : lane + kSlice - r;
       const int i = s * kSlice + li;
-      const bool ok = (d >= dlo) && (d < dlo + nd) && (i < nb);
-      const R rv = Rv[ok ? off + (int64_t)(d - dlo) * kSlice + li : 0];
-      const R g = gnus[ok ? i : 0];
-      acc = rfma<R>(ok ? rv : R(0), g, acc);
+      const bool ok = (dd >= dlo) && (dd < dlo + nd) && (i < nb);
+      const R x = Rv[ok ? off + (int64_t)(dd - dlo) * kSlice + li : 0];
+      const R y = gnus[ok ? i : 0];
+      rv = ok ? x : R(0);
+      g = y;
+    };
+    // Batches of kTailBatch loads issued together (the barrier keeps the
+    // scheduler from pairing each load with its FMA); same summation order.
+    for (; d + kTailBatch<R> <= dend; d += kTailBatch<R>) {
+      R x[kTailBatch<R>], y[kTailBatch<R>];
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) term(d + u, x[u], y[u]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
+    }
+    for (; d < dend; ++d) {
+      R x, y;
+      term(d, x, y);
+      acc = rfma<R>(x, y, acc);
     }
   }
   return acc;
 }
 
-template <class R, bool GRAD>
+template <class R, bool GRAD, bool SPLIT>
 __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
@@ -188,6 +208,19 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
   }
 
   const int nb = pd.n_bins;
+  if (SPLIT) {
+    // Split tail: every tile leaves its partial sums in the scratch region;
+    // the tail kernels read them after this launch.
+    R* sc = a.scratch + pd.scratch_off;
+    if (g == 0 && lb < pd.bins_per_tile && j < nb) {
+      sc[(int64_t)(td.chunk * 5) * nb + j] = mu;
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sc[(int64_t)(td.chunk * 5 + 1 + c) * nb + j] = J[c];
+      }
+    }
+    return;
+  }
   const int tiles_of_point = pd.n_bin_blocks * pd.C;
   const bool single = (tiles_of_point == 1);
   R* stage = L.stage<R>();
@@ -264,12 +297,26 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
     const int d0 = kap * csz, d1 = min(sd.nd, d0 + csz);
     const int i = s * kSlice + lane;
     const R* rv = a.Rv + sd.off + lane;
-    R acc = R(0);
-#pragma unroll 8
-    for (int dd = d0; dd < d1; ++dd) {
+    auto term = [&](int dd, R& x, R& y) {
       const int jj = i + sd.dlo + dd;
       const R m = mus[((unsigned)jj < (unsigned)nb) ? jj : 0];
-      acc = rfma<R>(rv[(int64_t)dd * kSlice], ((unsigned)jj < (unsigned)nb) ? m : R(0), acc);
+      x = rv[(int64_t)dd * kSlice];
+      y = ((unsigned)jj < (unsigned)nb) ? m : R(0);
+    };
+    R acc = R(0);
+    int dd = d0;
+    for (; dd + kTailBatch<R> <= d1; dd += kTailBatch<R>) {
+      R x[kTailBatch<R>], y[kTailBatch<R>];
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) term(dd + u, x[u], y[u]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
+    }
+    for (; dd < d1; ++dd) {
+      R x, y;
+      term(dd, x, y);
+      acc = rfma<R>(x, y, acc);
     }
     if (i < nb) part[kap * maxb + i] = acc;
   }
@@ -361,12 +408,12 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
   }
 }
 
-template <class R, bool GRAD, bool PERSIST>
+template <class R, bool GRAD, bool PERSIST, bool SPLIT>
 __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins, int split) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   TileLds L{lds_raw, (int)blockDim.x, max_bins, split};
   if (!PERSIST) {
-    process_tile<R, GRAD>(a, (int64_t)blockIdx.x, L);
+    process_tile<R, GRAD, SPLIT>(a, (int64_t)blockIdx.x, L);
     return;
   }
   __shared__ uint32_t next;
@@ -377,7 +424,7 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bin
     const int64_t t = next;
     __syncthreads();
     if (t >= a.n_tiles) break;
-    process_tile<R, GRAD>(a, t, L);
+    process_tile<R, GRAD, SPLIT>(a, t, L);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -392,10 +439,210 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bin
   }
 }
 
-template <class R, bool GRAD, bool PERSIST>
+// ---- split tail (uneven batches) ------------------------------------------
+// With a split tail the point pass above only writes every fit's bin sums;
+// three more launches finish the chain with the whole GPU on each step, one
+// wavefront per 64-row slice (forward) or 64-column block (adjoint) of every
+// fit, instead of one work-group per fit:
+//   tail_fwd    nu_i, the chi^2 terms and gnu_i of one slice
+//   tail_adj    gmu_j of one column block and its gradient sums
+//   tail_final  per fit: the slice and block partials added in a fixed order
+template <class R>
+struct TailArgs {
+  const ProbDev* probs;
+  const SliceDev* slices;
+  const int32_t* slice_prob;  // fit of each slice
+  int64_t n_items;            // slices of all fits (= column blocks)
+  int32_t n_fits;
+  const R* Rv;
+  const double* data;
+  const double* params;
+  const R* scratch;
+  R* gnu;                     // [total bins]  d chi2 / d nu
+  double* part;               // [n_items][6]  chi2 partial, 5 gradient partials
+  double* pred;
+  uint32_t* status;
+  double* chi2;
+  double* grad;
+};
+
+constexpr int kTailWaves = 4;    // wavefronts (items) per work-group
+constexpr int kWinDiag = 256;    // diagonals per staged window of mu
+
+template <class R>
+__device__ __forceinline__ R sum_chunks(const R* sc, int C, int comp, int nb, int j) {
+  R s = R(0);
+  for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5 + comp) * nb + j];
+  return s;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
+  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (item >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
+  R* win = win_all[wave];
+  const int f = a.slice_prob[item];
+  const ProbDev pd = a.probs[f];
+  const SliceDev sd = a.slices[item];
+  const int s = (int)(item - pd.slice_off);
+  const int nb = pd.n_bins;
+  const R* sc = a.scratch + pd.scratch_off;
+  const R normr = (R)a.params[5 * (int64_t)f + 4];
+  const int i = s * kSlice + lane;
+  const R* rv = a.Rv + sd.off + lane;
+  R acc = R(0);
+  for (int d0 = 0; d0 < sd.nd; d0 += kWinDiag) {
+    const int d1 = min(sd.nd, d0 + kWinDiag);
+    // Window of mu_j = norm * mu0_j over the columns these diagonals touch:
+    // column s*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1; zero outside the bins.
+    const int cbase = s * kSlice + sd.dlo + d0;
+    const int wn = kSlice + (d1 - d0) - 1;
+    for (int w = lane; w < wn; w += kWave) {
+      const int c = cbase + w;
+      win[w] = ((unsigned)c < (unsigned)nb) ? normr * sum_chunks<R>(sc, pd.C, 0, nb, c) : R(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int d = d0;
+    for (; d + kTailBatch<R> <= d1; d += kTailBatch<R>) {
+      R x[kTailBatch<R>], y[kTailBatch<R>];
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) {
+        x[u] = rv[(int64_t)(d + u) * kSlice];
+        y[u] = win[lane + d + u - d0];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
+    }
+    for (; d < d1; ++d) acc = rfma<R>(rv[(int64_t)d * kSlice], win[lane + d - d0], acc);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  double chi = 0.0;
+  bool badnu = false;
+  if (i < nb) {
+    const double nu = (double)acc;
+    const double d = a.data[pd.bin_off + i];
+    badnu = !(nu > 0.0) || !isfinite(nu);
+    const double ratio = d / nu;
+    chi = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
+    a.gnu[pd.bin_off + i] = (R)(2.0 * (1.0 - ratio));
+    if (a.pred) a.pred[pd.bin_off + i] = nu;
+  }
+  if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  chi = wave_sum(chi);
+  if (lane == 0) a.part[item * 6] = chi;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_adj_kernel(TailArgs<R> a) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (item >= a.n_items) return;
+  const int f = a.slice_prob[item];
+  const ProbDev pd = a.probs[f];
+  const int cb = (int)(item - pd.slice_off);
+  const int nb = pd.n_bins, ns = pd.n_slices;
+  const SliceDev* slices = a.slices + pd.slice_off;
+  // Diagonals that reach this column block from any slice.
+  int dmin = 1 << 30, dmax = -(1 << 30);
+  for (int s = 0; s < ns; ++s) {
+    const SliceDev sd = slices[s];
+    const int lo = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
+    const int hi = min(sd.dlo + sd.nd - 1, kSlice * (cb - s) + (kSlice - 1));
+    if (lo <= hi) {
+      dmin = min(dmin, lo);
+      dmax = max(dmax, hi);
+    }
+  }
+  R acc = R(0);
+  if (dmin <= dmax)
+    acc = adjoint_range<R>(a.Rv, slices, ns, nb, a.gnu + pd.bin_off, cb, lane, dmin, dmax + 1);
+  const int jc = cb * kSlice + lane;
+  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (jc < nb) {
+    const double gmu = (double)acc;
+    const R* sc = a.scratch + pd.scratch_off;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) gs[c] = gmu * (double)sum_chunks<R>(sc, pd.C, 1 + c, nb, jc);
+    gs[4] = gmu * (double)sum_chunks<R>(sc, pd.C, 0, nb, jc);
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a.part[item * 6 + 1 + c] = gs[c];
+  }
+}
+
+template <class R, bool GRAD>
+__global__ void __launch_bounds__(256) tail_final_kernel(TailArgs<R> a) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.n_fits) return;
+  const ProbDev pd = a.probs[f];
+  const double* th = a.params + 5 * (int64_t)f;
+  const bool bad = pee_coef<R>(th).bad;
+  double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < pd.n_slices; ++s) {
+    const double* q = a.part + (pd.slice_off + s) * 6;
+    chisum += q[0];
+    if (GRAD) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) g5[c] += q[1 + c];
+    }
+  }
+  if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  a.chi2[f] = bad ? NAN : 2.0 * chisum;
+  if (GRAD && a.grad) {
+    const double norm = th[4];
+    double* gp = a.grad + 5 * (int64_t)f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * g5[c];
+    gp[4] = bad ? NAN : g5[4];
+  }
+}
+
+template <class R>
+int launch_tail(gna_plan* p, const ChainArgs<R>& c, bool grad, hipStream_t s) {
+  unsigned char* w = p->ws;
+  TailArgs<R> a{};
+  a.probs = c.probs;
+  a.slices = c.slices;
+  a.slice_prob = (const int32_t*)(w + p->lay.slice_prob);
+  a.n_items = p->total_slices;
+  a.n_fits = p->n_points;
+  a.Rv = c.Rv;
+  a.data = c.data;
+  a.params = c.params;
+  a.scratch = c.scratch;
+  a.gnu = (R*)(w + p->lay.gnu);
+  a.part = (double*)(w + p->lay.tailpart);
+  a.pred = c.pred;
+  a.status = c.status;
+  a.chi2 = c.chi2;
+  a.grad = c.grad;
+  const unsigned g = (unsigned)((a.n_items + kTailWaves - 1) / kTailWaves);
+  hipLaunchKernelGGL(tail_fwd_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
+  if (grad) hipLaunchKernelGGL(tail_adj_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
+  const unsigned gf = (unsigned)((a.n_fits + 255) / 256);
+  if (grad)
+    hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((tail_final_kernel<R, false>), dim3(gf), dim3(256), 0, s, a);
+  return check_hip(hipGetLastError(), "tail kernel launch");
+}
+
+template <class R, bool GRAD, bool PERSIST, bool SPLIT>
 int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   const Shape& sh = p->shape;
-  auto kern = chain_kernel<R, GRAD, PERSIST>;
+  auto kern = chain_kernel<R, GRAD, PERSIST, SPLIT>;
   gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
   if (!lc.ready) {
     lc.lds = chain_lds_bytes(p, sh);
@@ -455,10 +702,19 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
   a.grad = grad;
   a.pred = pred;
   const bool pers = p->shape.persistent != 0;
-  if (grad) {
-    return pers ? launch_t<R, true, true>(p, a, s) : launch_t<R, true, false>(p, a, s);
+  if (p->shape.split) {
+    int rc;
+    if (grad)
+      rc = pers ? launch_t<R, true, true, true>(p, a, s) : launch_t<R, true, false, true>(p, a, s);
+    else
+      rc = pers ? launch_t<R, false, true, true>(p, a, s) : launch_t<R, false, false, true>(p, a, s);
+    if (rc) return rc;
+    return launch_tail<R>(p, a, grad != nullptr, s);
   }
-  return pers ? launch_t<R, false, true>(p, a, s) : launch_t<R, false, false>(p, a, s);
+  if (grad) {
+    return pers ? launch_t<R, true, true, false>(p, a, s) : launch_t<R, true, false, false>(p, a, s);
+  }
+  return pers ? launch_t<R, false, true, false>(p, a, s) : launch_t<R, false, false, false>(p, a, s);
 }
 
 }  // namespace

@@ -91,12 +91,13 @@ enum PlanKind { kChain = 0, kFitset = 1 };
 struct Layout {
   size_t probs = 0, slices = 0, slice_prob = 0, tiles = 0, E = 0, f = 0, L = 0, wL = 0,
          edges = 0, data = 0, gl = 0, Rv = 0, scratch = 0, counters = 0, queue = 0, status = 0,
-         Rdense = 0, total = 0;
+         Rdense = 0, gnu = 0, tailpart = 0, total = 0;
 };
 
 struct Shape {
   int threads = 256, G = 1, C = 1, persistent = 0, mfma = 0;
   int share = 1;  // MFMA kernel: tiles with common dm2 share their phases (if the plan allows)
+  int split = 0;  // uneven batch: the tail runs in its own launches, wide over the GPU
 };
 
 }  // namespace gna

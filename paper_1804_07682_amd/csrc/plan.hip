@@ -304,6 +304,7 @@ int chain_split(const gna_plan* p, const Shape& sh) {
 }
 
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
+  if (sh.split) return 0;  // the point pass alone keeps nothing in LDS
   const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
   const int split = chain_split(p, sh);
   const size_t part = split > 1 ? align_up((size_t)split * p->max_bins * rs, 16) : 0;
@@ -345,6 +346,7 @@ Shape auto_shape(const gna_plan* p) {
     sh.C = std::max(1, std::min(want, cmax));
   } else {
     sh.C = 1;
+    sh.split = 1;
   }
   sh.persistent = 0;
   sh.mfma = 0;
@@ -366,16 +368,18 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
       if (p->kind == kFitset && t / G < 4) continue;
       for (int C : Cs) {
         if (C > p->ccap || C > ppb / G + 1) continue;
-        for (int pers = 0; pers <= 1; ++pers) {
-          Shape sh;
-          sh.threads = t;
-          sh.G = G;
-          sh.C = C;
-          sh.persistent = pers;
-          sh.mfma = 0;
-          if (chain_lds_bytes(p, sh) > p->lds_limit) continue;
-          out.push_back(sh);
-        }
+        for (int pers = 0; pers <= 1; ++pers)
+          for (int split = 0; split <= (p->kind == kFitset ? 1 : 0); ++split) {
+            Shape sh;
+            sh.threads = t;
+            sh.G = G;
+            sh.C = C;
+            sh.persistent = pers;
+            sh.mfma = 0;
+            sh.split = split;
+            if (chain_lds_bytes(p, sh) > p->lds_limit) continue;
+            out.push_back(sh);
+          }
       }
     }
   if (p->kind == kChain && scan_supported(p)) {
@@ -396,6 +400,8 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
   if (sh.G < 1 || sh.G > kWave || (sh.G & (sh.G - 1)) || sh.G > sh.threads)
     return fail(GNA_E_INVAL, "lanes_per_bin = %d invalid", sh.G);
   if (sh.C < 1) return fail(GNA_E_INVAL, "chunks = %d invalid", sh.C);
+  if (sh.split && p->kind != kFitset)
+    return fail(GNA_E_UNSUPPORTED, "a split tail needs a fitset plan");
   if (sh.mfma && !(p->kind == kChain && scan_supported(p)))
     return fail(GNA_E_UNSUPPORTED, "MFMA smearing needs a chain plan with n_bins <= 256");
   if (!sh.mfma && chain_lds_bytes(p, sh) > p->lds_limit)
@@ -500,6 +506,8 @@ void compute_layout(gna_plan* p, PlanBuild& b) {
   L.queue = take(16);
   L.status = take(16);
   L.Rdense = take(p->kind == kChain ? scan_dense_bytes(p) : 0);
+  L.gnu = take(p->kind == kFitset ? rs * p->total_bins : 0);
+  L.tailpart = take(p->kind == kFitset ? 6 * 8 * p->total_slices : 0);
   L.total = off;
 }
 
@@ -542,6 +550,10 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       return fail(GNA_E_INVAL, "opts.smear_mfma = %d not in -1..3", opts->smear_mfma);
     if (opts->no_shared_phases < 0 || opts->no_shared_phases > 1)
       return fail(GNA_E_INVAL, "opts.no_shared_phases = %d not 0/1", opts->no_shared_phases);
+    if (opts->split_tail < 0 || opts->split_tail > 2)
+      return fail(GNA_E_INVAL, "opts.split_tail = %d not in 0..2", opts->split_tail);
+    if (opts->split_tail == 2 && kind != kFitset)
+      return fail(GNA_E_INVAL, "opts.split_tail = 2 needs a fitset plan");
   }
   for (int i = 0; i < n_probs; ++i) {
     rc = validate_problem(problems + i, i);
@@ -628,6 +640,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
     if (opts->chunks) sh.C = opts->chunks;
     sh.persistent = opts->persistent;
     if (opts->smear_mfma >= 1) sh.mfma = opts->smear_mfma;
+    if (opts->split_tail) sh.split = opts->split_tail == 2;
   }
   if (kind == kChain && (!opts || opts->smear_mfma == -1) && scan_supported(p) &&
       n_points >= 64)
@@ -834,7 +847,7 @@ extern "C" int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_sta
   return GNA_OK;
 }
 
-extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_t* n_tiles) {
+extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[7], int64_t* n_tiles) {
   clear_error();
   if (!plan) return fail(GNA_E_INVAL, "plan is NULL");
   if (shape_out) {
@@ -844,6 +857,7 @@ extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[6], int64_
     shape_out[3] = plan->shape.persistent;
     shape_out[4] = plan->shape.mfma;
     shape_out[5] = plan->share_phases;
+    shape_out[6] = plan->shape.split;
   }
   if (n_tiles) *n_tiles = plan->n_tiles;
   return GNA_OK;

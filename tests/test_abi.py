@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_strings(lib):
-    assert lib.gna_abi_version() == 3
+    assert lib.gna_abi_version() == 4
     for code in (0, -1, -2, -3, -4, -5, 17):
         assert lib.gna_strerror(code)
     assert lib.gna_strerror(-4).decode().startswith("workspace")
@@ -119,6 +119,8 @@ def test_chain_validation_errors(lib):
     assert _sizes(lib, pr, B=0)[0] == -1
     assert _sizes(lib, pr, opts={"threads": 100})[0] == -1
     assert _sizes(lib, pr, opts={"lanes_per_bin": 3})[0] == -1
+    assert _sizes(lib, pr, opts={"split_tail": 3})[0] == -1
+    assert _sizes(lib, pr, opts={"split_tail": 2})[0] == -1  # chain plans have no split tail
     big = W.problem(W.uniform_edges(5000), 3, [52.5])
     big["data"] = np.ones(5000)
     assert _sizes(lib, big)[0] == -1

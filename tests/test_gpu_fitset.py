@@ -62,18 +62,44 @@ def test_fitset_fp64_parity(small_set):
     assert fs.status() == 0
 
 
+@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
 @pytest.mark.parametrize("opts", [
     dict(threads=64, lanes_per_bin=1, chunks=1),
     dict(threads=128, lanes_per_bin=2, chunks=3, persistent=1),
     dict(threads=256, lanes_per_bin=4, chunks=2),
     dict(threads=512, lanes_per_bin=1, chunks=4, persistent=1),
 ])
-def test_fitset_shapes(small_set, opts):
+def test_fitset_shapes(small_set, opts, tail):
     problems, params = small_set
-    _, got = _run(problems, params, **opts)
+    fs, got = _run(problems, params, split_tail=tail, **opts)
+    assert fs.shape()["split_tail"] == tail - 1
     chi2, grad = oracle.fitset(problems, MODEL, params, n_threads=8)
     assert np.max(rel_err(got["chi2"], chi2)) <= FP64_RTOL
     assert np.max(grad_error(got["grad"], grad, params, chi2)) <= FP64_RTOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fitset_split_tail_wide_band(prec):
+    """Fits whose band is wider than one staged window of mu (3001 bins: up
+    to ~370 diagonals per slice) and fits of a single slice (<= 64 bins), in
+    both tails, against the oracle; pred from both tails agrees."""
+    problems = [W.problem(W.uniform_edges(3001), 3, [52.5]),
+                W.problem(W.uniform_edges(50), 4, [1.0, 700.0]),
+                W.problem(W.uniform_edges(2600), 2, [300.0]),
+                W.problem(W.uniform_edges(64), 3, [52.5])]
+    problems = _with_data(problems)
+    params = np.array(W.THETA0) * np.array([[1.0] * 5, [1.1, 0.9, 1.0, 1.05, 0.95],
+                                            [0.9] * 5, [1.05] * 5])
+    chi2, grad = oracle.fitset(problems, MODEL, params, n_threads=8)
+    outs = []
+    for tail in (1, 2):
+        fs, got = _run(problems, params, prec=prec, pred=True, split_tail=tail)
+        assert fs.shape()["split_tail"] == tail - 1
+        tc, tg = (FP64_RTOL, FP64_RTOL) if prec == "fp64" else (MIXED_CHI2_RTOL, MIXED_GRAD_TOL)
+        assert np.max(rel_err(got["chi2"], chi2)) <= tc
+        assert np.max(grad_error(got["grad"], grad, params, chi2)) <= tg
+        outs.append(got["pred"])
+    assert np.max(rel_err(outs[1], outs[0])) <= (1e-13 if prec == "fp64" else 1e-6)
 
 
 def test_fitset_mixed(small_set):
@@ -93,14 +119,14 @@ def test_fitset_autotune_keeps_results(small_set, tmp_path):
     a = fs.eval(P)["chi2"].cpu().numpy()
     cache = tmp_path / "tune.json"
     shape = fs.autotune(P, reps=2, cache_path=cache)
-    assert cache.exists() and shape["threads"] in (64, 128, 256, 512)
+    assert cache.exists() and shape["threads"] in (64, 128, 256, 512, 1024)
     b = fs.eval(P)["chi2"].cpu().numpy()
     assert np.max(rel_err(b, a)) <= 1e-13
     # A second plan of the same bucket reads the cache instead of timing.
     fs2 = gna.FitSet(problems, MODEL, prec="fp64", device=DEV)
     shape2 = fs2.autotune(P, reps=2, cache_path=cache)
-    assert {k: shape2[k] for k in ("threads", "lanes_per_bin", "chunks", "persistent")} == \
-        {k: shape[k] for k in ("threads", "lanes_per_bin", "chunks", "persistent")}
+    keys = ("threads", "lanes_per_bin", "chunks", "persistent", "split_tail")
+    assert {k: shape2[k] for k in keys} == {k: shape[k] for k in keys}
 
 
 def test_fitset_full_size_sampled():

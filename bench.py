@@ -291,7 +291,8 @@ def bench_fitset(gna, W, torch, timer, dev, steps, prec):
         off += nb
     plan = gna.FitSet(problems, model, prec=prec, device=dev)
     P = torch.tensor(params, device=dev)
-    plan.autotune(P, reps=3)
+    if TUNE:
+        plan.autotune(P, reps=3)
     wall, _, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
     kmean = timer.period
     return {"fits_per_s": len(problems) * steps / wall, "kernel_ms": kmean * 1e3,

@@ -146,8 +146,15 @@ __device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict_
   return acc;
 }
 
+// Baseline constants of the current tile's problem, staged once per tile so
+// the per-baseline loop reads LDS (a broadcast) instead of waiting on memory.
+struct BaseLds {
+  double kl[kMaxBaselines];  // K L_r
+  double w[kMaxBaselines];   // w_r
+};
+
 template <class R, bool GRAD, bool SPLIT>
-__device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L) {
+__device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L, BaseLds& bl) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
   TileDev td;
@@ -163,7 +170,12 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
   }
   const ProbDev pd = a.probs[td.prob];
   const double* th = a.params + 5 * (int64_t)td.point;
+  for (int r = tid; r < pd.n_L; r += NT) {
+    bl.kl[r] = kPhase * a.L[pd.L_off + r];
+    bl.w[r] = a.wL[pd.L_off + r];
+  }
   const PeeCoef<R> k = pee_coef<R>(th);
+  __syncthreads();
 
   // ---- point pass --------------------------------------------------------
   const int G = pd.G;
@@ -175,14 +187,30 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L)
   R J[4] = {R(0), R(0), R(0), R(0)};
   if (lb < pd.bins_per_tile && j < pd.n_bins) {
     const int64_t base = pd.pt_off + (int64_t)j * pd.ppb;
-    for (int kk = k0 + g; kk < k1; kk += G) {
-      const double E = a.E[base + kk];
-      const R fk = a.f[base + kk];
+    const int nL = pd.n_L;
+    // Software-pipelined: the next point's E and f and the next baseline's
+    // constants are requested before the current evaluation.
+    int kk = k0 + g;
+    double En = (kk < k1) ? a.E[base + kk] : 1.0;
+    R fn = (kk < k1) ? a.f[base + kk] : R(0);
+    for (; kk < k1; kk += G) {
+      const double E = En;
+      const R fk = fn;
+      if (kk + G < k1) {
+        En = a.E[base + kk + G];
+        fn = a.f[base + kk + G];
+      }
       R pb = R(0);
       R dpb[4] = {R(0), R(0), R(0), R(0)};
-      for (int r = 0; r < pd.n_L; ++r) {
-        const double q = phase_per_ev2(kPhase * a.L[pd.L_off + r], E);
-        const R wr = (R)a.wL[pd.L_off + r];
+      double kln = bl.kl[0], wn = bl.w[0];
+      for (int r = 0; r < nL; ++r) {
+        const double klr = kln, wrd = wn;
+        const int rn = (r + 1 < nL) ? r + 1 : r;
+        kln = bl.kl[rn];
+        wn = bl.w[rn];
+        __builtin_amdgcn_sched_barrier(0);  // keep the request ahead of the math
+        const double q = phase_per_ev2(klr, E);
+        const R wr = (R)wrd;
         R P, dP[4];
         pee_point<R, GRAD>(k, q, P, dP);
         pb = rfma<R>(wr, P, pb);
@@ -412,8 +440,9 @@ template <class R, bool GRAD, bool PERSIST, bool SPLIT>
 __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins, int split) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   TileLds L{lds_raw, (int)blockDim.x, max_bins, split};
+  __shared__ BaseLds bl;
   if (!PERSIST) {
-    process_tile<R, GRAD, SPLIT>(a, (int64_t)blockIdx.x, L);
+    process_tile<R, GRAD, SPLIT>(a, (int64_t)blockIdx.x, L, bl);
     return;
   }
   __shared__ uint32_t next;
@@ -424,7 +453,7 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bin
     const int64_t t = next;
     __syncthreads();
     if (t >= a.n_tiles) break;
-    process_tile<R, GRAD, SPLIT>(a, t, L);
+    process_tile<R, GRAD, SPLIT>(a, t, L, bl);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -451,10 +480,12 @@ template <class R>
 struct TailArgs {
   const ProbDev* probs;
   const SliceDev* slices;
+  const SliceDev* tslices;    // 64-column blocks of the transposed band
   const int32_t* slice_prob;  // fit of each slice
   int64_t n_items;            // slices of all fits (= column blocks)
   int32_t n_fits;
   const R* Rv;
+  const R* RTv;
   const double* data;
   const double* params;
   const R* scratch;
@@ -476,32 +507,24 @@ __device__ __forceinline__ R sum_chunks(const R* sc, int C, int comp, int nb, in
   return s;
 }
 
-template <class R>
-__global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
-  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
-  if (item >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
-  R* win = win_all[wave];
-  const int f = a.slice_prob[item];
-  const ProbDev pd = a.probs[f];
-  const SliceDev sd = a.slices[item];
-  const int s = (int)(item - pd.slice_off);
-  const int nb = pd.n_bins;
-  const R* sc = a.scratch + pd.scratch_off;
-  const R normr = (R)a.params[5 * (int64_t)f + 4];
-  const int i = s * kSlice + lane;
-  const R* rv = a.Rv + sd.off + lane;
+// acc_l = sum_d B[l][d] v[64 blk + dlo + d + l] for one 64-row block of a
+// band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l), summed
+// over d in ascending order.  v comes from vat(c) for 0 <= c < n and is 0
+// elsewhere; it is staged per wavefront in LDS, kWinDiag diagonals at a time.
+template <class R, class V>
+__device__ __forceinline__ R band_block_dot(const R* __restrict__ Bv, const SliceDev& sd, int blk,
+                                            int lane, int n, R* win, V vat) {
+  const R* bv = Bv + sd.off + lane;
   R acc = R(0);
   for (int d0 = 0; d0 < sd.nd; d0 += kWinDiag) {
     const int d1 = min(sd.nd, d0 + kWinDiag);
-    // Window of mu_j = norm * mu0_j over the columns these diagonals touch:
-    // column s*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1; zero outside the bins.
-    const int cbase = s * kSlice + sd.dlo + d0;
+    // Window over the vector entries these diagonals touch: index
+    // blk*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1.
+    const int cbase = blk * kSlice + sd.dlo + d0;
     const int wn = kSlice + (d1 - d0) - 1;
     for (int w = lane; w < wn; w += kWave) {
       const int c = cbase + w;
-      win[w] = ((unsigned)c < (unsigned)nb) ? normr * sum_chunks<R>(sc, pd.C, 0, nb, c) : R(0);
+      win[w] = ((unsigned)c < (unsigned)n) ? vat(c) : R(0);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -511,18 +534,37 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
       R x[kTailBatch<R>], y[kTailBatch<R>];
 #pragma unroll
       for (int u = 0; u < kTailBatch<R>; ++u) {
-        x[u] = rv[(int64_t)(d + u) * kSlice];
+        x[u] = bv[(int64_t)(d + u) * kSlice];
         y[u] = win[lane + d + u - d0];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
     }
-    for (; d < d1; ++d) acc = rfma<R>(rv[(int64_t)d * kSlice], win[lane + d - d0], acc);
+    for (; d < d1; ++d) acc = rfma<R>(bv[(int64_t)d * kSlice], win[lane + d - d0], acc);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  return acc;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
+  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (item >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
+  const int f = a.slice_prob[item];
+  const ProbDev pd = a.probs[f];
+  const int s = (int)(item - pd.slice_off);
+  const int nb = pd.n_bins, C = pd.C;
+  const R* sc = a.scratch + pd.scratch_off;
+  const R normr = (R)a.params[5 * (int64_t)f + 4];
+  // nu_i = sum_j R_ij mu_j with mu_j = norm * mu0_j.
+  const R acc = band_block_dot<R>(a.Rv, a.slices[item], s, lane, nb, win_all[wave],
+                                  [&](int c) { return normr * sum_chunks<R>(sc, C, 0, nb, c); });
+  const int i = s * kSlice + lane;
   double chi = 0.0;
   bool badnu = false;
   if (i < nb) {
@@ -542,36 +584,26 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
 
 template <class R>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_adj_kernel(TailArgs<R> a) {
+  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
   const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
   if (item >= a.n_items) return;
   const int f = a.slice_prob[item];
   const ProbDev pd = a.probs[f];
   const int cb = (int)(item - pd.slice_off);
-  const int nb = pd.n_bins, ns = pd.n_slices;
-  const SliceDev* slices = a.slices + pd.slice_off;
-  // Diagonals that reach this column block from any slice.
-  int dmin = 1 << 30, dmax = -(1 << 30);
-  for (int s = 0; s < ns; ++s) {
-    const SliceDev sd = slices[s];
-    const int lo = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
-    const int hi = min(sd.dlo + sd.nd - 1, kSlice * (cb - s) + (kSlice - 1));
-    if (lo <= hi) {
-      dmin = min(dmin, lo);
-      dmax = max(dmax, hi);
-    }
-  }
-  R acc = R(0);
-  if (dmin <= dmax)
-    acc = adjoint_range<R>(a.Rv, slices, ns, nb, a.gnu + pd.bin_off, cb, lane, dmin, dmax + 1);
+  const int nb = pd.n_bins, C = pd.C;
+  // gmu_j = sum_i R_ij gnu_i, walked along the transposed band.
+  const R* gn = a.gnu + pd.bin_off;
+  const R acc = band_block_dot<R>(a.RTv, a.tslices[item], cb, lane, nb, win_all[wave],
+                                  [&](int c) { return gn[c]; });
   const int jc = cb * kSlice + lane;
   double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (jc < nb) {
     const double gmu = (double)acc;
     const R* sc = a.scratch + pd.scratch_off;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) gs[c] = gmu * (double)sum_chunks<R>(sc, pd.C, 1 + c, nb, jc);
-    gs[4] = gmu * (double)sum_chunks<R>(sc, pd.C, 0, nb, jc);
+    for (int c = 0; c < 4; ++c) gs[c] = gmu * (double)sum_chunks<R>(sc, C, 1 + c, nb, jc);
+    gs[4] = gmu * (double)sum_chunks<R>(sc, C, 0, nb, jc);
   }
 #pragma unroll
   for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
@@ -581,31 +613,35 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_adj_kernel(TailArgs<R
   }
 }
 
+// One wavefront per fit: lane s takes slice / column block s (a fit has at
+// most kMaxBins / 64 = 64 of them), and the butterfly sums are fixed-order.
 template <class R, bool GRAD>
-__global__ void __launch_bounds__(256) tail_final_kernel(TailArgs<R> a) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs<R> a) {
+  static_assert(kMaxBins <= kSlice * kWave, "one lane per slice");
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  const int f = blockIdx.x * kTailWaves + wave;
   if (f >= a.n_fits) return;
   const ProbDev pd = a.probs[f];
   const double* th = a.params + 5 * (int64_t)f;
-  const bool bad = pee_coef<R>(th).bad;
-  double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < pd.n_slices; ++s) {
-    const double* q = a.part + (pd.slice_off + s) * 6;
-    chisum += q[0];
-    if (GRAD) {
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (lane < pd.n_slices) {
+    const double* q = a.part + (pd.slice_off + lane) * 6;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) g5[c] += q[1 + c];
-    }
+    for (int c = 0; c < (GRAD ? 6 : 1); ++c) v[c] = q[c];
   }
+#pragma unroll
+  for (int c = 0; c < (GRAD ? 6 : 1); ++c) v[c] = wave_sum(v[c]);
+  if (lane != 0) return;
+  const bool bad = pee_coef<R>(th).bad;
   if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
-  a.chi2[f] = bad ? NAN : 2.0 * chisum;
+  a.chi2[f] = bad ? NAN : 2.0 * v[0];
   if (GRAD && a.grad) {
     const double norm = th[4];
     double* gp = a.grad + 5 * (int64_t)f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * g5[c];
-    gp[4] = bad ? NAN : g5[4];
+    for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * v[1 + c];
+    gp[4] = bad ? NAN : v[5];
   }
 }
 
@@ -615,10 +651,12 @@ int launch_tail(gna_plan* p, const ChainArgs<R>& c, bool grad, hipStream_t s) {
   TailArgs<R> a{};
   a.probs = c.probs;
   a.slices = c.slices;
+  a.tslices = (const SliceDev*)(w + p->lay.tslices);
   a.slice_prob = (const int32_t*)(w + p->lay.slice_prob);
   a.n_items = p->total_slices;
   a.n_fits = p->n_points;
   a.Rv = c.Rv;
+  a.RTv = (const R*)(w + p->lay.RTv);
   a.data = c.data;
   a.params = c.params;
   a.scratch = c.scratch;
@@ -631,11 +669,12 @@ int launch_tail(gna_plan* p, const ChainArgs<R>& c, bool grad, hipStream_t s) {
   const unsigned g = (unsigned)((a.n_items + kTailWaves - 1) / kTailWaves);
   hipLaunchKernelGGL(tail_fwd_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
   if (grad) hipLaunchKernelGGL(tail_adj_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
-  const unsigned gf = (unsigned)((a.n_fits + 255) / 256);
+  const unsigned gf = (unsigned)((a.n_fits + kTailWaves - 1) / kTailWaves);
   if (grad)
-    hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), dim3(kTailWaves * kWave), 0, s, a);
   else
-    hipLaunchKernelGGL((tail_final_kernel<R, false>), dim3(gf), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((tail_final_kernel<R, false>), dim3(gf), dim3(kTailWaves * kWave), 0, s,
+                       a);
   return check_hip(hipGetLastError(), "tail kernel launch");
 }
 

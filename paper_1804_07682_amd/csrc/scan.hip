@@ -197,7 +197,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   const int bg = tid >> 4;           // bin group
   const int lane = tid & (kWave - 1), wave = tid >> 6;
   const int krow = lane >> 4;        // k index of this lane in an MFMA operand
-  // Lanes per bin for the shared sums: a power of two, at most 16.
+  // Lanes per bin for the shared sums: the largest power of two, at most 16,
+  // with which one pass over the bins covers them all (G nb <= NT).
   int G = 1;
   while (G < 16 && 2 * G * nb <= NT) G *= 2;
   const int items = a.ppb * nL;

@@ -482,6 +482,7 @@ struct TailArgs {
   const SliceDev* slices;
   const SliceDev* tslices;    // 64-column blocks of the transposed band
   const int32_t* slice_prob;  // fit of each slice
+  const int32_t* order;       // the launch's items, longest first
   int64_t n_items;            // slices of all fits (= column blocks)
   int32_t n_fits;
   const R* Rv;
@@ -553,8 +554,9 @@ template <class R>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
   __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
-  if (item >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
+  const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (idx >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
+  const int64_t item = a.order[idx];
   const int f = a.slice_prob[item];
   const ProbDev pd = a.probs[f];
   const int s = (int)(item - pd.slice_off);
@@ -586,8 +588,9 @@ template <class R>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_adj_kernel(TailArgs<R> a) {
   __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int64_t item = (int64_t)blockIdx.x * kTailWaves + wave;
-  if (item >= a.n_items) return;
+  const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (idx >= a.n_items) return;
+  const int64_t item = a.order[idx];
   const int f = a.slice_prob[item];
   const ProbDev pd = a.probs[f];
   const int cb = (int)(item - pd.slice_off);
@@ -667,8 +670,12 @@ int launch_tail(gna_plan* p, const ChainArgs<R>& c, bool grad, hipStream_t s) {
   a.chi2 = c.chi2;
   a.grad = c.grad;
   const unsigned g = (unsigned)((a.n_items + kTailWaves - 1) / kTailWaves);
+  a.order = (const int32_t*)(w + p->lay.fwd_order);
   hipLaunchKernelGGL(tail_fwd_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
-  if (grad) hipLaunchKernelGGL(tail_adj_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
+  if (grad) {
+    a.order = (const int32_t*)(w + p->lay.adj_order);
+    hipLaunchKernelGGL(tail_adj_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
+  }
   const unsigned gf = (unsigned)((a.n_fits + kTailWaves - 1) / kTailWaves);
   if (grad)
     hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), dim3(kTailWaves * kWave), 0, s, a);

@@ -91,7 +91,8 @@ enum PlanKind { kChain = 0, kFitset = 1 };
 struct Layout {
   size_t probs = 0, slices = 0, slice_prob = 0, tiles = 0, E = 0, f = 0, L = 0, wL = 0,
          edges = 0, data = 0, gl = 0, Rv = 0, scratch = 0, counters = 0, queue = 0, status = 0,
-         Rdense = 0, gnu = 0, tailpart = 0, tslices = 0, RTv = 0, total = 0;
+         Rdense = 0, gnu = 0, tailpart = 0, tslices = 0, RTv = 0, fwd_order = 0, adj_order = 0,
+         total = 0;
 };
 
 struct Shape {
@@ -143,6 +144,8 @@ struct gna_plan {
   std::vector<gna::ProbDev> probs;     // host copy of the device descriptors
   std::vector<gna::SliceDev> slices;   // host copy
   std::vector<gna::SliceDev> tslices;  // fitset: 64-column blocks of the transposed band
+  std::vector<int32_t> fwd_order;      // fitset: slices, most diagonals first
+  std::vector<int32_t> adj_order;      // fitset: column blocks, most diagonals first
   std::vector<double> edges_host;      // concatenated edges
 };
 

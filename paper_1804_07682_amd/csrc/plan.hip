@@ -538,6 +538,8 @@ void compute_layout(gna_plan* p, PlanBuild& b) {
   L.tailpart = take(p->kind == kFitset ? 6 * 8 * p->total_slices : 0);
   L.tslices = take(p->kind == kFitset ? sizeof(SliceDev) * p->tslices.size() : 0);
   L.RTv = take(p->kind == kFitset ? rs * p->total_tband : 0);
+  L.fwd_order = take(4 * p->fwd_order.size());
+  L.adj_order = take(4 * p->adj_order.size());
   L.total = off;
 }
 
@@ -666,6 +668,18 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->total_slices = slices;
   p->total_band = band;
   p->total_tband = tband;
+  if (kind == kFitset) {
+    // Tail work items in longest-first order (each item's cost is its number
+    // of diagonals), so the wide launches do not end on a few long items.
+    auto lpt = [](const std::vector<SliceDev>& v, std::vector<int32_t>& out) {
+      out.resize(v.size());
+      for (size_t i = 0; i < v.size(); ++i) out[i] = (int32_t)i;
+      std::stable_sort(out.begin(), out.end(),
+                       [&](int32_t a, int32_t b) { return v[a].nd > v[b].nd; });
+    };
+    lpt(p->slices, p->fwd_order);
+    lpt(p->tslices, p->adj_order);
+  }
   p->edges_host = b.edges;
   // Chunk cap, scratch and tile capacity for every shape the plan may run.
   if (opts && opts->chunks > 0)
@@ -737,7 +751,9 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
   if ((rc = up(L.slices, p->slices.data(), sizeof(SliceDev) * p->slices.size()))) return rc;
   if ((rc = up(L.slice_prob, b.slice_prob.data(), 4 * b.slice_prob.size()))) return rc;
   if (p->kind == kFitset &&
-      (rc = up(L.tslices, p->tslices.data(), sizeof(SliceDev) * p->tslices.size())))
+      ((rc = up(L.tslices, p->tslices.data(), sizeof(SliceDev) * p->tslices.size())) ||
+       (rc = up(L.fwd_order, p->fwd_order.data(), 4 * p->fwd_order.size())) ||
+       (rc = up(L.adj_order, p->adj_order.data(), 4 * p->adj_order.size()))))
     return rc;
   if ((rc = up(L.L, b.L.data(), 8 * b.L.size()))) return rc;
   if ((rc = up(L.wL, b.wL.data(), 8 * b.wL.size()))) return rc;

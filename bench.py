@@ -587,7 +587,7 @@ def main():
         line["chain_8L"] = {p: bench_chain_single(gna, W, torch, timer, dev, W.config2,
                                                   W.SEED + 2, 200, p) for p in ("fp64", "mixed")}
         log("fitset ...")
-        line["fitset"] = {p: bench_fitset(gna, W, torch, timer, dev, 10, p)
+        line["fitset"] = {p: bench_fitset(gna, W, torch, timer, dev, 50, p)
                           for p in ("fp64", "mixed")}
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)

@@ -141,3 +141,50 @@ def test_fitset_full_size_sampled():
         tc, tg = (FP64_RTOL, FP64_RTOL) if prec == "fp64" else (MIXED_CHI2_RTOL, MIXED_GRAD_TOL)
         assert np.max(rel_err(got["chi2"][idx], chi2)) <= tc
         assert np.max(grad_error(got["grad"][idx], grad, params[idx], chi2)) <= tg
+
+
+@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
+def test_fitset_without_gradient_and_domain_errors(small_set, tail):
+    """chi2 and pred without the gradient pass; a fit with s12 outside [0, 1]
+    gets NaN and latches the status word, the others are unaffected; a fit
+    whose prediction is 0 (norm = 0) latches it too."""
+    import paper_1804_07682_amd as gna
+    problems, params = small_set
+    fs = gna.FitSet(problems, MODEL, prec="fp64", opts={"split_tail": tail}, device=DEV)
+    P = params.copy()
+    out = fs.eval(torch.tensor(P, device=DEV), grad=False, pred=True)
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    assert "grad" not in got or got["grad"] is None
+    chi2 = oracle.fitset(problems, MODEL, P, grad=False, n_threads=8)
+    assert np.max(rel_err(got["chi2"], chi2)) <= FP64_RTOL
+    nb0 = len(problems[0]["edges"]) - 1
+    nu0 = oracle.chain(problems[0], MODEL, P[0], grad=False, nu=True)["nu"][0]
+    assert np.max(rel_err(got["pred"][:nb0], nu0)) <= FP64_RTOL
+    assert fs.status() == 0
+    P[3, 2] = 1.5
+    got = fs.eval(torch.tensor(P, device=DEV), grad=True)
+    c, g = got["chi2"].cpu().numpy(), got["grad"].cpu().numpy()
+    assert np.isnan(c[3]) and np.all(np.isnan(g[3]))
+    ok = np.arange(len(problems)) != 3
+    assert np.max(rel_err(c[ok], chi2[ok])) <= FP64_RTOL
+    with pytest.raises(gna.GnaError):
+        fs.status()
+    assert fs.status() == 0
+    P = params.copy()
+    P[5, 4] = 0.0
+    fs.eval(torch.tensor(P, device=DEV), grad=True)
+    with pytest.raises(gna.GnaError):
+        fs.status()
+
+
+@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
+@pytest.mark.parametrize("nb", [1, 63, 64, 65])
+def test_fitset_single_fit_edge_sizes(tail, nb):
+    """One fit of 1, 63, 64 or 65 bins (one slice, a full slice, a ragged
+    second slice) in both tails, against the oracle."""
+    problems = _with_data([W.problem(W.uniform_edges(nb), 3, [52.5, 700.0])])
+    params = np.atleast_2d(W.THETA0 * np.array([1.02, 0.98, 1.01, 0.99, 1.0]))
+    _, got = _run(problems, params, pred=True, split_tail=tail)
+    chi2, grad = oracle.fitset(problems, MODEL, params, n_threads=1)
+    assert np.max(rel_err(got["chi2"], chi2)) <= FP64_RTOL
+    assert np.max(grad_error(got["grad"], grad, params, chi2)) <= FP64_RTOL

@@ -37,8 +37,8 @@ __device__ __forceinline__ float rfma<float>(float a, float b, float c) {
   return __builtin_fmaf(a, b, c);
 }
 
-// Band loads issued back to back in the smearing loops of the tail (32
-// VGPRs of operands either way).
+// Band loads issued back to back in the smearing loops (32 VGPRs of
+// operands either way; 16 FP64 loads measured no faster).
 template <class R>
 constexpr int kTailBatch = sizeof(R) == 8 ? 8 : 16;
 

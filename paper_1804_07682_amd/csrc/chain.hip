@@ -146,6 +146,24 @@ __device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict_
   return acc;
 }
 
+// sum over chunks c < C of sc[(c*5 + comp)*nb + j], added in the order
+// c = 0, 1, ...: the loads of eight chunks are issued before any is added
+// (the partials come from other work-groups, so each load is a trip to
+// memory); missing chunks of the last eight add exact zeros.
+template <class R>
+__device__ __forceinline__ R sum_chunks(const R* sc, int C, int comp, int nb, int j) {
+  R s = R(0);
+  for (int c = 0; c < C; c += 8) {
+    R v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = (c + u < C) ? sc[(int64_t)((c + u) * 5 + comp) * nb + j] : R(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  return s;
+}
+
 // Baseline constants of the current tile's problem, staged once per tile so
 // the per-baseline loop reads LDS (a broadcast) instead of waiting on memory.
 struct BaseLds {
@@ -181,11 +199,41 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   const int G = pd.G;
   const int lb = tid / G, g = tid - (tid / G) * G;
   const int j = td.bb * pd.bins_per_tile + lb;
-  const int k0 = (int)((int64_t)td.chunk * pd.ppb / pd.C);
-  const int k1 = (int)((int64_t)(td.chunk + 1) * pd.ppb / pd.C);
+  // Chunk td.chunk of the bin's units: points, or (point, baseline) items
+  // it = kk n_L + r when the plan splits items.
+  const int units = pd.by_item ? pd.ppb * pd.n_L : pd.ppb;
+  const int k0 = (int)((int64_t)td.chunk * units / pd.C);
+  const int k1 = (int)((int64_t)(td.chunk + 1) * units / pd.C);
   R mu = R(0);
   R J[4] = {R(0), R(0), R(0), R(0)};
-  if (lb < pd.bins_per_tile && j < pd.n_bins) {
+  if (lb < pd.bins_per_tile && j < pd.n_bins && pd.by_item) {
+    // One evaluation per trip: lane g takes items k0 + g, k0 + g + G, ...;
+    // (kk, r) step by G = gq n_L + gr without a division per item.
+    const int64_t base = pd.pt_off + (int64_t)j * pd.ppb;
+    const int nL = pd.n_L;
+    const int gq = G / nL, gr = G - (G / nL) * nL;
+    int it = k0 + g;
+    int kk = it / nL, r = it - (it / nL) * nL;
+    for (; it < k1; it += G) {
+      const double E = a.E[base + kk];
+      const R fk = a.f[base + kk];
+      const double q = phase_per_ev2(bl.kl[r], E);
+      const R fw = fk * (R)bl.w[r];
+      R P, dP[4];
+      pee_point<R, GRAD>(k, q, P, dP);
+      mu = rfma<R>(fw, P, mu);
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) J[c] = rfma<R>(fw, dP[c], J[c]);
+      }
+      kk += gq;
+      r += gr;
+      if (r >= nL) {
+        r -= nL;
+        ++kk;
+      }
+    }
+  } else if (lb < pd.bins_per_tile && j < pd.n_bins) {
     const int64_t base = pd.pt_off + (int64_t)j * pd.ppb;
     const int nL = pd.n_L;
     // Software-pipelined: the next point's E and f and the next baseline's
@@ -270,7 +318,12 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   }
   int* flag = L.flag<R>();
   if (!single) {
-    __threadfence();  // release this tile's partial sums at agent scope
+    // Release this tile's partial sums at agent scope with one L2 write-back
+    // per tile instead of one per wavefront: each wavefront first waits
+    // until its own stores are acknowledged by the L2 (the barrier alone does
+    // not wait for them), then thread 0's release-acquire increment writes
+    // the L2 back before it counts the tile.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (tid == 0) {
       const uint32_t prev = __hip_atomic_fetch_add(&a.counters[td.point], 1u, __ATOMIC_ACQ_REL,
@@ -279,7 +332,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     }
     __syncthreads();
     if (*flag == 0) return;  // not the last tile of this point
-    __threadfence();         // acquire the other tiles' partial sums
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other tiles' partial sums
     if (tid == 0) a.counters[td.point] = 0u;  // ready for the next evaluation
   } else {
     __syncthreads();
@@ -288,16 +341,10 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   // ---- tail ----------------------------------------------------------------
   const int C = pd.C;
   auto mu0_of = [&](int jj) -> R {
-    if (single) return stage[jj * 5];
-    R s = R(0);
-    for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5) * nb + jj];
-    return s;
+    return single ? stage[jj * 5] : sum_chunks<R>(sc, C, 0, nb, jj);
   };
   auto J0_of = [&](int jj, int cidx) -> R {
-    if (single) return stage[jj * 5 + 1 + cidx];
-    R s = R(0);
-    for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5 + 1 + cidx) * nb + jj];
-    return s;
+    return single ? stage[jj * 5 + 1 + cidx] : sum_chunks<R>(sc, C, 1 + cidx, nb, jj);
   };
   const double norm = th[4];
   const R normr = (R)norm;
@@ -500,13 +547,6 @@ struct TailArgs {
 
 constexpr int kTailWaves = 4;    // wavefronts (items) per work-group
 constexpr int kWinDiag = 256;    // diagonals per staged window of mu
-
-template <class R>
-__device__ __forceinline__ R sum_chunks(const R* sc, int C, int comp, int nb, int j) {
-  R s = R(0);
-  for (int c = 0; c < C; ++c) s += sc[(int64_t)(c * 5 + comp) * nb + j];
-  return s;
-}
 
 // acc_l = sum_d B[l][d] v[64 blk + dlo + d + l] for one 64-row block of a
 // band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l), summed

@@ -34,6 +34,8 @@ struct ProbDev {
   int32_t bins_per_tile;  // threads / G
   int32_t n_bin_blocks;
   int32_t n_slices;
+  int32_t by_item;        // lanes and chunks split (point, baseline) items, not points
+  int32_t pad_;
   int64_t pt_off;         // first quadrature point (E, f arrays)
   int64_t bin_off;        // first bin in data / pred (fitset) arrays
   int64_t edge_off;       // first edge

@@ -395,7 +395,8 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
       if (G > t || G > 2 * ppb) continue;
       if (p->kind == kFitset && t / G < 4) continue;
       for (int C : Cs) {
-        if (C > p->ccap || C > ppb / G + 1) continue;
+        // Beyond one point per lane the lanes split (point, baseline) items.
+        if (C > p->ccap || C > ppb * nL / G + 1) continue;
         for (int pers = 0; pers <= 1; ++pers)
           for (int split = 0; split <= (p->kind == kFitset ? 1 : 0); ++split) {
             Shape sh;
@@ -441,7 +442,11 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
     pd.G = sh.G;
     pd.bins_per_tile = sh.threads / sh.G;
     pd.n_bin_blocks = (pd.n_bins + pd.bins_per_tile - 1) / pd.bins_per_tile;
-    pd.C = std::max(1, std::min(std::min(sh.C, pd.ppb), p->ccap));
+    // With fewer than two points per lane and several baselines, lanes and
+    // chunks take (point, baseline) items instead of whole points.
+    pd.by_item = (pd.n_L > 1 && (int64_t)pd.ppb < 2LL * sh.G * sh.C) ? 1 : 0;
+    const int units = pd.by_item ? pd.ppb * pd.n_L : pd.ppb;
+    pd.C = std::max(1, std::min(std::min(sh.C, units), p->ccap));
   }
   if (p->kind == kChain) {
     p->n_tiles = (int64_t)p->probs[0].n_bin_blocks * p->probs[0].C;
@@ -456,13 +461,15 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
       for (int bb = 0; bb < pd.n_bin_blocks; ++bb) {
         const int nbins = std::min(pd.bins_per_tile, pd.n_bins - bb * pd.bins_per_tile);
         for (int c = 0; c < pd.C; ++c) {
-          const int k0 = (int)((int64_t)c * pd.ppb / pd.C);
-          const int k1 = (int)((int64_t)(c + 1) * pd.ppb / pd.C);
-          // Lanes of one bin share its points: the tile lasts ceil(points / G) trips.
+          const int units = pd.by_item ? pd.ppb * pd.n_L : pd.ppb;
+          const int k0 = (int)((int64_t)c * units / pd.C);
+          const int k1 = (int)((int64_t)(c + 1) * units / pd.C);
+          // Lanes of one bin share its points (or items): the tile lasts
+          // ceil(units / G) trips of n_L (or one) evaluations.
           const double trips = std::ceil((double)(k1 - k0) / pd.G);
           Item it;
           it.t = TileDev{(int32_t)i, (int32_t)i, bb, c};
-          it.cost = trips * pd.n_L + 1e-6 * nbins;
+          it.cost = trips * (pd.by_item ? 1 : pd.n_L) + 1e-6 * nbins;
           items.push_back(it);
         }
       }
@@ -694,7 +701,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
     p->scratch_elems = (int64_t)n_points * p->ccap * 5 * p->probs[0].n_bins;
   } else {
     for (auto& pd : p->probs) {
-      const int c = std::min(p->ccap, pd.ppb);
+      const int c = std::min(p->ccap, pd.ppb * pd.n_L);
       pd.scratch_off = p->scratch_elems;
       p->scratch_elems += (int64_t)c * 5 * pd.n_bins;
       p->tile_capacity += (int64_t)((pd.n_bins + 3) / 4) * c;

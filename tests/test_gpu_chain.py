@@ -110,6 +110,27 @@ def test_cfg2_full_chain(cfg2, prec):
         assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= MIXED_GRAD_TOL
 
 
+@pytest.fixture(scope="module")
+def cfg2_ref(cfg2):
+    P = np.atleast_2d(THETAS[1])
+    return P, oracle.chain(cfg2, MODEL, P, grad=True, nu=True)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(threads=256, lanes_per_bin=64, chunks=1),              # whole points per lane
+    dict(threads=512, lanes_per_bin=64, chunks=8),              # (point, baseline) items
+    dict(threads=256, lanes_per_bin=32, chunks=16, persistent=1),
+    dict(threads=1024, lanes_per_bin=16, chunks=32),
+], ids=["points", "items_c8", "items_c16_persistent", "items_c32"])
+def test_cfg2_point_and_item_split(cfg2, cfg2_ref, opts):
+    """8 baselines, 420 points per bin: lanes walking whole points and lanes
+    taking (point, baseline) items, over up to 32 chunks (many tiles handing
+    off to the last one), all against the oracle."""
+    P, ref = cfg2_ref
+    plan = _plan(cfg2, smear_mfma=0, **opts)
+    _check_fp64(_eval(plan, P), ref, P)
+
+
 def test_batch_matches_single_points_and_oracle(cfg0):
     P = W.config3_params(8, 8)
     plan = _plan(cfg0, B=64, smear_mfma=0)

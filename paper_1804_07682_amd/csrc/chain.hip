@@ -404,7 +404,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     const double nu = (double)acc;
     const double d = dat[i];
     if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-    const double ratio = d / nu;
+    const double ratio = quot_pos(d, nu);
     chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
     gnus[i] = (R)(2.0 * (1.0 - ratio));
     if (pred) pred[i] = nu;
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
     const double nu = (double)acc;
     const double d = a.data[pd.bin_off + i];
     badnu = !(nu > 0.0) || !isfinite(nu);
-    const double ratio = d / nu;
+    const double ratio = quot_pos(d, nu);
     chi = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
     a.gnu[pd.bin_off + i] = (R)(2.0 * (1.0 - ratio));
     if (a.pred) a.pred[pd.bin_off + i] = nu;

@@ -58,6 +58,11 @@ __device__ __forceinline__ double phase_per_ev2(double KL, double E) {
   return dfma(dfma(-E, q, KL), y, q);
 }
 
+// a / b for b > 0, rounded to nearest in the normal range (the same
+// reciprocal-and-correction steps as the phase quotient above); NaN for b <= 0
+// or NaN.  Shorter dependent chain than the IEEE division sequence.
+__device__ __forceinline__ double quot_pos(double a, double b) { return phase_per_ev2(a, b); }
+
 // q = KL / E within ~2 ulp (mixed precision: the phase needs ~1e-13 relative).
 __device__ __forceinline__ double phase_per_ev2_fast(double KL, double E) {
   return KL * recip_pos(E);

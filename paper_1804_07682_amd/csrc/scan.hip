@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         const double nu = norm * si;
         const double d = in ? d_s[i] : 0.0;
         badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
-        const double ratio = d / nu;
+        const double ratio = quot_pos(d, nu);
         const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
         chi += in ? term : 0.0;
         if (GRAD) {
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             const double nu = (double)acc[u][v];
             const double d = d_s[i];
             badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
-            const double ratio = d / nu;
+            const double ratio = quot_pos(d, nu);
             const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
             chi += in ? term : 0.0;
             bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);

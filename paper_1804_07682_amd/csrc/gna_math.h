@@ -199,6 +199,29 @@ __device__ __forceinline__ PhaseTerms<R> phase_terms(double phi) {
   return out;
 }
 
+// Terms of phi32 = phi31 - phi21 from those of phi21 and phi31 by the
+// angle-difference formulas for the doubled angles (cos 2phi = C - S,
+// sin 2phi = T):
+//   cos 2phi32 = (C31 - S31)(C21 - S21) + T31 T21,
+//   sin 2phi32 = T31 (C21 - S21) - (C31 - S31) T21,
+//   S32 = (1 - cos 2phi32) / 2,   C32 = (1 + cos 2phi32) / 2.
+// A third reduction and polynomial pair is replaced by a few products; the
+// implied phase is phi31 - phi21 of the two rounded phases, which differs
+// from (dm2_31 - dm2_21) q by a few ulps of phi31.  Mixed precision only:
+// at 1300 km that difference moves FP64 gradients by ~1e-12 relative, so
+// FP64 evaluates phi32 itself (the oracle's operation order).
+template <class R>
+__device__ __forceinline__ PhaseTerms<R> phase_terms_diff(const PhaseTerms<R>& t21,
+                                                          const PhaseTerms<R>& t31) {
+  const R u21 = t21.C - t21.S, u31 = t31.C - t31.S;
+  const R c2 = rfma_t<R>(u31, u21, t31.T * t21.T);
+  PhaseTerms<R> out;
+  out.T = rfma_t<R>(t31.T, u21, -(u31 * t21.T));
+  out.S = rfma_t<R>(R(-0.5), c2, R(0.5));
+  out.C = rfma_t<R>(R(0.5), c2, R(0.5));
+  return out;
+}
+
 // Per-parameter-point coefficients of P_ee written in the all-positive form
 //   P = K0 + A cos^2 phi21 + B1 cos^2 phi31 + B2 cos^2 phi32,
 //   A = 4 s12 (1-s12) (1-s13)^2, B = 4 s13 (1-s13), B1 = B (1-s12), B2 = B s12,
@@ -244,10 +267,9 @@ __device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
 
 // P_ee and its four parameter derivatives at phase-per-eV^2 q, with the
 // trigonometric terms of phase i (0: phi21, 1: phi31, 2: phi32) given by
-// terms(i).  Each phase's terms are folded into P and the tangents as soon as
-// they are available, which keeps few values live at once; every caller, be
-// it computing the terms in place or reading them from a table, performs the
-// same operations in the same order and so gets the same bits.
+// terms(i) (in mixed precision those of phi32 are derived from the other
+// two).  Each phase's terms are folded into P and the tangents as soon as
+// they are available, which keeps few values live at once.
 template <class R, bool GRAD, class Terms>
 __device__ __forceinline__ void pee_accumulate(const PeeCoef<R>& k, R qr, Terms terms, R& P,
                                                R dP[4]) {
@@ -266,7 +288,7 @@ __device__ __forceinline__ void pee_accumulate(const PeeCoef<R>& k, R qr, Terms 
     d2 = rfma_t<R>(k.B, t31.S, d2);
     d3 = d3 - k.dB13 * (k.c12 * t31.S);
   }
-  const PhaseTerms<R> t32 = terms(2);
+  const PhaseTerms<R> t32 = sizeof(R) == 4 ? phase_terms_diff<R>(t21, t31) : terms(2);
   P = rfma_t<R>(k.B2, t32.C, p);
   if (GRAD) {
     const R bt = k.B2 * t32.T;

@@ -95,6 +95,28 @@ __device__ __forceinline__ void copy16(void* dst, const void* src, size_t bytes)
   for (int i = threadIdx.x; i < n16; i += NT) d[i] = g[i];
 }
 
+// The same copy with direct-to-LDS loads (global_load_lds_dwordx4): every
+// wavefront instruction moves 1 KB (lane l's 16 bytes land at dst + 16 l)
+// without passing through registers, and the copy completes in the
+// background.  The tail below 1 KB goes through registers.  Before dst is
+// read, every wavefront waits for its loads (s_waitcnt vmcnt(0)) and then
+// the work-group meets at a barrier.  dst, src and bytes: multiples of 16.
+template <int NT>
+__device__ __forceinline__ void copy16_async(void* dst, const void* src, size_t bytes) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const size_t nk = bytes >> 10;
+  const unsigned char* g = reinterpret_cast<const unsigned char*>(src);
+  unsigned char* d = reinterpret_cast<unsigned char*>(dst);
+  // The tail first: its register round trip must not wait for the DMA.
+  const size_t done = nk << 10;
+  if (bytes > done) copy16<NT>(d + done, g + done, bytes - done);
+  for (size_t c = wave; c < nk; c += NW)
+    __builtin_amdgcn_global_load_lds(
+        g + (c << 10) + lane * 16,
+        (__attribute__((address_space(3))) void*)(d + (c << 10)), 16, 0, 0);
+}
+
 // Per-bin sums of the phase terms that a tile of points with common
 // (dm2_21, dm2_31) shares; see the kernel.
 constexpr int kTab = 10;
@@ -184,7 +206,6 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
     p_s[tid] = a.params[5 * (int64_t)pp + tid % 5];
   }
   for (int i = tid; i < scan_meta_ints(mt); i += NT) meta[i] = a.meta[i];
-  if (a.rlds) copy16<NT>(Rs, a.band, (size_t)a.nblk * kBlk * sizeof(R));
   if ((nL * nq) % 2 == 0)
     copy16<NT>(q_s, a.qtab, (size_t)nL * nq * 8);
   else
@@ -193,6 +214,9 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
   for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
   __syncthreads();
+  // The band is needed only from the smearing on: its copy runs while the
+  // point pass computes (issued after the barrier, which would wait for it).
+  if (a.rlds) copy16_async<NT>(Rs, a.band, (size_t)a.nblk * kBlk * sizeof(R));
 
   const int bg = tid >> 4;           // bin group
   const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -329,6 +353,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
       }
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wavefront's band copy
     __syncthreads();
 
     // ---- 2. nu = R mu ---------------------------------------------------------

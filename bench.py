@@ -88,11 +88,15 @@ def log(msg):
 
 
 def source_hash():
-    """Hash of the kernel sources: counter readings are valid only for this build."""
+    """Hash of the kernel sources with comments and blank space removed:
+    counter readings are valid only for this code (a comment edit keeps them)."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1804_07682_amd", "csrc", "*"))):
         if f.endswith((".hip", ".h")):
-            h.update(open(f, "rb").read())
+            text = open(f).read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -4,13 +4,17 @@
 //
 // Work decomposition.  A tile is (parameter point, block of bins, chunk of
 // each bin's quadrature points).  Inside a tile, G lanes share a bin: each
-// lane walks the bin's points (all baselines, Fig. 4) and accumulates
+// lane walks the bin's points (all baselines, Fig. 4), or, when a bin has
+// fewer than two points per lane, its (point, baseline) items, and
+// accumulates
 //   mu0_j = sum_k f_k Pbar_k   and   J0_jc = sum_k f_k d Pbar_k / d theta_c,
 // then the G lanes are summed with cross-lane shuffles.  When a point's bins
 // fit one tile the results stay in LDS; otherwise each tile writes its
 // partial sums to the scratch region and the last tile of the point (agent-
 // scope counter, release/acquire fences) adds the chunks in a fixed order and
-// runs the tail.  Results are therefore independent of scheduling.
+// runs the tail.  Results are therefore independent of scheduling.  An
+// uneven batch can instead split the tail off into wide launches over all
+// fits (tail_fwd / tail_adj / tail_final below).
 //
 // Tail (one work-group per point):
 //   nu_i    = sum_j R_ij mu_j          banded R, one wavefront per 64-row slice

@@ -106,6 +106,39 @@ __device__ __forceinline__ double log_pos(double x) {
   return x == 0.0 ? -__builtin_huge_val() : (x > 0.0 ? x : __builtin_nan(""));
 }
 
+// Natural logarithm with a table of 257 entries (a table-driven reduction):
+// x = m 2^e with m in [sqrt(1/2), sqrt(2)); k = floor(362 m - 255.5) in
+// [0, 256] picks c_k = (k + 256) / 362 (c_106 = 1 exactly); tab[2k] = r_k, the
+// double nearest 1 / c_k, and tab[2k+1] = -ln r_k to the nearest double (both
+// computed once on the host); f = m r_k - 1 is rounded once (|f| <= 0.002) and
+//   ln x = e ln 2 + (-ln r_k) + log1p(f),  log1p(f) = f - f^2/2 + ... - f^6/6,
+// the dropped terms below 2e-20.  Within a few ulp; near x = 1, k = 106 and
+// r_k = 1, so nothing cancels.  Same special cases as log_pos (the index is
+// clamped so that they read the table in bounds).
+constexpr int kLogTab = 257;
+
+__device__ __forceinline__ double log_tab(double x, const double* tab) {
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  if (m < 0.70710678118654752440) {
+    m = m + m;
+    e -= 1;
+  }
+  int k = (int)dfma(m, 362.0, -255.5);
+  k = k < 0 ? 0 : (k > kLogTab - 1 ? kLogTab - 1 : k);
+  const double r = tab[2 * k], mlr = tab[2 * k + 1];
+  const double f = dfma(m, r, -1.0);
+  double p = dfma(f, -1.0 / 6, 0.2);
+  p = dfma(f, p, -0.25);
+  p = dfma(f, p, 1.0 / 3);
+  p = dfma(f, p, -0.5);
+  const double l1 = dfma(f * f, p, f);
+  const double de = (double)e;
+  const double lx = dfma(de, 0x1.62e42fefa3800p-1, dfma(de, 0x1.ef35793c76730p-45, mlr + l1));
+  if (x > 0.0 && x < __builtin_huge_val()) return lx;
+  return x == 0.0 ? -__builtin_huge_val() : (x > 0.0 ? x : __builtin_nan(""));
+}
+
 // sin r, cos r on |r| <= pi/4 (minimax kernels from trig_coeffs.h).
 __device__ __forceinline__ void sincos_kernel(double r, double& s, double& c) {
   const double x = r * r;

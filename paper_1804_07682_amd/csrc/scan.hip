@@ -59,6 +59,7 @@ template <class R>
 struct ScanArgs {
   int32_t B, nb, mt, ppb, nL, nq;
   const double* qtab;  // [nL][nq]  q = (K L_r) / E_k
+  const double* logtab;  // [kLogTab][2] table of the chi^2 logarithm
   const R* f;          // [nq]
   const double* wL;    // [nL]
   const double* data;  // [nb]
@@ -83,6 +84,15 @@ __host__ __device__ inline size_t a16(size_t x) { return (x + 15) & ~size_t(15);
 __host__ __device__ inline int scan_meta_ints(int mt) { return 5 * mt + mt * mt; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Logarithm of the chi^2 terms: the table-driven one in the mixed-precision
+// kernels (fewer instructions; measured 4% faster there), the series one in
+// FP64, whose kernels sit at the register limit (the table's address and
+// operands made them spill).
+template <class R>
+__device__ __forceinline__ double chi2_log(double x, const double* tab) {
+  return sizeof(R) == 4 ? log_tab(x, tab) : log_pos(x);
+}
 
 // dst[0, bytes) = src[0, bytes) by the work-group, 16 bytes a lane, with
 // several loads in flight per lane (both 16-byte aligned; bytes % 16 == 0).
@@ -133,7 +143,7 @@ __host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, i
          a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
          a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
          a16((size_t)nwaves * kScanN * 6 * 8) + (share ? a16((size_t)mt * 16 * kTab * 8) : 0) +
-         a16((size_t)rblocks * kBlk * sizeof(R));
+         a16((size_t)kLogTab * 16) + a16((size_t)rblocks * kBlk * sizeof(R));
 }
 
 template <class T>
@@ -193,6 +203,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   cur += a16((size_t)NW * kScanN * 6 * 8);
   double* mm = reinterpret_cast<double*>(cur);  // [nbp][kTab] M = R T of a shared tile
   cur += SHARE ? a16((size_t)nbp * kTab * 8) : 0;
+  double* lt_s = reinterpret_cast<double*>(cur);  // [kLogTab][2] logarithm table
+  cur += a16((size_t)kLogTab * 16);
   R* Rs = reinterpret_cast<R*>(cur);  // [nblk][16][kRowPad] the band of R (if a.rlds)
 
   const int tid = threadIdx.x;
@@ -213,6 +225,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   for (int i = tid; i < nq; i += NT) f_s[i] = a.f[i];
   for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
   for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
+  if (sizeof(R) == 4) copy16<NT>(lt_s, a.logtab, (size_t)kLogTab * 16);
   __syncthreads();
   // The band is needed only from the smearing on: its copy runs while the
   // point pass computes (issued after the barrier, which would wait for it).
@@ -429,7 +442,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         const double d = in ? d_s[i] : 0.0;
         badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
         const double ratio = quot_pos(d, nu);
-        const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
+        const double term = dfma(d, chi2_log<R>(d > 0.0 ? ratio : 1.0, lt_s), nu - d);
         chi += in ? term : 0.0;
         if (GRAD) {
           const double gn = in ? 2.0 * (1.0 - ratio) : 0.0;
@@ -485,7 +498,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             const double d = d_s[i];
             badnu |= in && !(nu > 0.0 && nu < __builtin_huge_val());
             const double ratio = quot_pos(d, nu);
-            const double term = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);
+            const double term = dfma(d, chi2_log<R>(d > 0.0 ? ratio : 1.0, lt_s), nu - d);
             chi += in ? term : 0.0;
             bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
           }
@@ -689,7 +702,7 @@ __global__ void pack_band_kernel(const R* __restrict__ RA, const int32_t* __rest
 }
 
 struct ScanLayout {
-  size_t RA, RT, meta, blist, band, qtab, total;
+  size_t RA, RT, meta, blist, band, qtab, logtab, total;
 };
 
 ScanLayout scan_layout(const gna_plan* p) {
@@ -710,6 +723,7 @@ ScanLayout scan_layout(const gna_plan* p) {
   L.blist = take((size_t)mt * mt * 2 * 4);
   L.band = take((size_t)mt * mt * kBlk * rs);
   L.qtab = take((size_t)pd.n_L * nq * 8);
+  L.logtab = take((size_t)kLogTab * 16);
   L.total = off;
   return L;
 }
@@ -795,6 +809,7 @@ int launch_scan_r(gna_plan* p, const double* params, int32_t B, double* chi2, do
   a.nL = pd.n_L;
   a.nq = pd.n_bins * pd.ppb;
   a.qtab = (const double*)(base + SL.qtab);
+  a.logtab = (const double*)(base + SL.logtab);
   a.f = (const R*)(w + p->lay.f);
   a.wL = (const double*)(w + p->lay.wL);
   a.data = (const double*)(w + p->lay.data);
@@ -879,6 +894,16 @@ int build_scan_tables(gna_plan* p, hipStream_t s) {
   meta.insert(meta.end(), blkT.begin(), blkT.end());
   int rc = check_hip(hipMemcpyAsync(base + SL.meta, meta.data(), meta.size() * 4,
                                     hipMemcpyHostToDevice, s), "hipMemcpyAsync (scan index tables)");
+  if (rc) return rc;
+  // Logarithm table (log_tab): r_k = 362 / (k + 256) rounded once, and
+  // -ln r_k from a long-double logarithm, rounded once.
+  std::vector<double> lt(2 * kLogTab);
+  for (int k = 0; k < kLogTab; ++k) {
+    lt[2 * k] = 362.0 / (double)(k + 256);
+    lt[2 * k + 1] = (double)(-std::log((long double)lt[2 * k]));
+  }
+  rc = check_hip(hipMemcpyAsync(base + SL.logtab, lt.data(), lt.size() * 8, hipMemcpyHostToDevice,
+                                s), "hipMemcpyAsync (logarithm table)");
   if (rc) return rc;
   if (nblk > 0) {
     rc = check_hip(hipMemcpyAsync(base + SL.blist, blist.data(), blist.size() * 4,

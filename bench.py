@@ -15,6 +15,8 @@ The same JSON line also carries, measured in this run:
     point evaluates its own phases), mixed and FP64;
   * pee: elementwise P_ee over N = 1e8 energies (52.5 km) in FP64 and mixed,
     evaluations/s and HBM bandwidth against 8 TB/s;
+  * pee_sweep: the same over N in {1e6, 1e7, 1e8} and L in {1, 52.5, 1300} km,
+    with the mixed-vs-FP64 error per baseline;
   * chain_1pt / chain_8L / fitset: the single-point chain (1200 points), the
     single-point chain with 8 baselines and 100 800 points, and the uneven
     batch of 1024 fits (evaluations/s, FP64 and mixed); the single-point
@@ -223,6 +225,31 @@ def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
     res["hbm_frac"] = res["GBps"] / HBM_PEAK_GBPS
     del E, out
     return res
+
+
+def pee_sweep(gna, W, torch, timer, dev):
+    """Elementwise P_ee over N in {1e6, 1e7, 1e8} energies and L in {1, 52.5,
+    1300} km, FP64 and mixed: GB/s per case (only N = 1e8 exceeds the 256 MB
+    Infinity Cache; 1e6 is launch-bound) and the largest relative error of
+    mixed against FP64 per baseline (N = 1e6)."""
+    out = {}
+    for n in (10 ** 6, 10 ** 7, 10 ** 8):
+        for L in (1.0, 52.5, 1300.0):
+            key = f"N={n:.0e} L={L:g}"
+            out[key] = {}
+            for prec in ("fp64", "mixed"):
+                r = bench_pee(gna, W, torch, timer, dev, n, L, prec, 20 if n == 10 ** 8 else 100)
+                out[key][prec] = {"GBps": round(r["GBps"], 1), "hbm_frac": round(r["hbm_frac"], 4),
+                                  "kernel_us": round(r["kernel_ms"] * 1e3, 2)}
+    err = {}
+    E = torch.from_numpy(W.config1_energies(10 ** 6)).to(dev)
+    for L in (1.0, 52.5, 1300.0):
+        a = gna.gna_pee(E, L, W.THETA0, prec="fp64").cpu().numpy()
+        b = gna.gna_pee(E, L, W.THETA0, prec="mixed").double().cpu().numpy()
+        err[f"L={L:g}"] = {"max_rel": float(np.max(np.abs(b - a) / np.abs(a))),
+                           "max_abs": float(np.max(np.abs(b - a)))}
+    out["mixed_vs_fp64"] = err
+    return out
 
 
 def copy_probe(gna, torch, timer, dev, n=10 ** 8, steps=20):
@@ -585,6 +612,8 @@ def main():
             pee[prec]["traffic"] = measured_traffic(key)
         pee["workload"] = "N=1e8 energies uniform in [1.8, 12] MeV, L=52.5 km, one parameter point"
         line["pee"] = pee
+        log("P_ee sweep over N and L ...")
+        line["pee_sweep"] = pee_sweep(gna, W, torch, timer, dev)
         log("single-point chains ...")
         line["chain_1pt"] = {p: bench_chain_single(gna, W, torch, timer, dev, W.config0, W.SEED,
                                                    400, p) for p in ("fp64", "mixed")}

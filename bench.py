@@ -58,6 +58,9 @@ ALU_PEAK_TFLOPS = 78.6
 # sin 2phi (1), i.e. 40 x 3; P (6); tangents (18); baseline weight (10);
 # flux factor (10).
 FLOPS_PER_PEE_GRAD_EVAL = 167
+# The generic chain kernel computes the phase q = (K L) / E per (quadrature
+# point, baseline) itself (a reciprocal-based quotient, counted as 2).
+FLOPS_PER_CHAIN_ITEM = FLOPS_PER_PEE_GRAD_EVAL + 2
 # A tile of 16 points with common (dm2_21, dm2_31) shares its phases: per
 # (quadrature point, baseline) item the three phases' terms (3 x 40), the
 # weights f w and f w q (2) and 10 weighted bin sums (19); per (parameter
@@ -277,6 +280,12 @@ def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec)
     wall, kpair, _ = timer.run(lambda: plan.eval(P, grad=True, out=out), steps, 10)
     res = {"evals_per_s": steps / wall, "launch_period_us": timer.period * 1e6,
            "event_pair_us": kpair * 1e6, "shape": plan.shape()}
+    # Point-pass work against the ALU peak (the smearing tail is not counted).
+    items = (len(pr["edges"]) - 1) * int(pr["gl_order"]) * int(pr.get("n_sub", 1)) * len(pr["L"])
+    flops = items * FLOPS_PER_CHAIN_ITEM
+    res["alu"] = {"flops_per_eval": flops, "achieved_tflops": flops / timer.period / 1e12,
+                  "frac": flops / timer.period / 1e12 / ALU_PEAK_TFLOPS,
+                  "flop_model": f"{FLOPS_PER_CHAIN_ITEM} per (quadrature point, baseline)"}
     res["graph"] = graph_rate(torch, lambda: plan.eval(P, grad=True, out=out), steps)
     return res
 

@@ -240,9 +240,9 @@ __device__ __forceinline__ PhaseTerms<R> phase_terms(double phi) {
 //   S32 = (1 - cos 2phi32) / 2,   C32 = (1 + cos 2phi32) / 2.
 // A third reduction and polynomial pair is replaced by a few products; the
 // implied phase is phi31 - phi21 of the two rounded phases, which differs
-// from (dm2_31 - dm2_21) q by a few ulps of phi31.  Mixed precision only:
-// at 1300 km that difference moves FP64 gradients by ~1e-12 relative, so
-// FP64 evaluates phi32 itself (the oracle's operation order).
+// from (dm2_31 - dm2_21) q by a few ulps of phi31: harmless in mixed
+// precision, but at 1300 km it moves FP64 gradients by ~1e-12 relative, so
+// FP64 corrects it (phase_terms_diff64 below).
 template <class R>
 __device__ __forceinline__ PhaseTerms<R> phase_terms_diff(const PhaseTerms<R>& t21,
                                                           const PhaseTerms<R>& t31) {
@@ -270,6 +270,7 @@ __device__ __forceinline__ PhaseTerms<R> phase_terms_diff(const PhaseTerms<R>& t
 template <class R>
 struct PeeCoef {
   double dm21, dm31, dm32;
+  double dm32e;  // (dm2_31 - dm2_21) - dm32, the exact error of the subtraction
   R K0, A, B, B1, B2, s12, c12, dA12, dA13, dB13;
   bool bad;
 };
@@ -280,6 +281,11 @@ __device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
   k.dm21 = th[0];
   k.dm31 = th[1];
   k.dm32 = th[1] - th[0];
+  {  // two-sum: the subtraction's rounding error, exactly
+    const double a = th[1], b = -th[0];
+    const double bb = k.dm32 - a;
+    k.dm32e = (a - (k.dm32 - bb)) + (b - bb);
+  }
   const double s12 = th[2], s13 = th[3];
   k.bad = !(s12 >= 0.0 && s12 <= 1.0 && s13 >= 0.0 && s13 <= 1.0);
   const double c13 = 1.0 - s13, c12 = 1.0 - s12;
@@ -298,11 +304,42 @@ __device__ __forceinline__ PeeCoef<R> pee_coef(const double* th) {
   return k;
 }
 
+// FP64 terms of phi32 = RN(dm32 q) from those of phi21 and phi31.  The
+// doubled-angle formulas of phase_terms_diff give the terms of theta =
+// phi31 - phi21 of the two rounded phases, which differs from phi32 by
+//   Delta = phi32 - theta = -e q + (r31 - r21) - r32,
+// with r_ij = dm2_ij q - phi_ij the exact residuals of the three products (by
+// FMA) and e the exact error of dm32 = dm2_31 - dm2_21; every term is below
+// ~1e-12 rad, so rotating the doubled angle by 2 Delta to first order,
+//   cos 2phi32 = cos 2theta - 2 Delta sin 2theta,
+//   sin 2phi32 = sin 2theta + 2 Delta cos 2theta,
+// leaves an error near 1e-24: the terms are those of the oracle's phi32 to a
+// few ulps, for about half the work of a third reduction and polynomial pair.
+template <class R>
+__device__ __forceinline__ PhaseTerms<double> phase_terms_diff64(const PhaseTerms<double>& t21,
+                                                                 const PhaseTerms<double>& t31,
+                                                                 double q, const PeeCoef<R>& k) {
+  const double p21 = k.dm21 * q, p31 = k.dm31 * q, p32 = k.dm32 * q;
+  const double r21 = dfma(k.dm21, q, -p21), r31 = dfma(k.dm31, q, -p31);
+  const double r32 = dfma(k.dm32, q, -p32);
+  const double d2 = 2.0 * dfma(-k.dm32e, q, (r31 - r21) - r32);
+  const double u21 = t21.C - t21.S, u31 = t31.C - t31.S;
+  const double c2 = dfma(u31, u21, t31.T * t21.T);
+  const double s2 = dfma(t31.T, u21, -(u31 * t21.T));
+  const double c2r = dfma(-d2, s2, c2);
+  PhaseTerms<double> out;
+  out.T = dfma(d2, c2, s2);
+  out.S = dfma(-0.5, c2r, 0.5);
+  out.C = dfma(0.5, c2r, 0.5);
+  return out;
+}
+
 // P_ee and its four parameter derivatives at phase-per-eV^2 q, with the
-// trigonometric terms of phase i (0: phi21, 1: phi31, 2: phi32) given by
-// terms(i) (in mixed precision those of phi32 are derived from the other
-// two).  Each phase's terms are folded into P and the tangents as soon as
-// they are available, which keeps few values live at once.
+// trigonometric terms of phase i (0: phi21, 1: phi31) given by terms(i) and
+// those of phi32 derived from the two (phase_terms_diff, and in FP64 with the
+// correction to RN(dm32 q) of phase_terms_diff64).  Each phase's terms are
+// folded into P and the tangents as soon as they are available, which keeps
+// few values live at once.
 template <class R, bool GRAD, class Terms>
 __device__ __forceinline__ void pee_accumulate(const PeeCoef<R>& k, R qr, Terms terms, R& P,
                                                R dP[4]) {
@@ -321,7 +358,11 @@ __device__ __forceinline__ void pee_accumulate(const PeeCoef<R>& k, R qr, Terms 
     d2 = rfma_t<R>(k.B, t31.S, d2);
     d3 = d3 - k.dB13 * (k.c12 * t31.S);
   }
-  const PhaseTerms<R> t32 = sizeof(R) == 4 ? phase_terms_diff<R>(t21, t31) : terms(2);
+  PhaseTerms<R> t32;
+  if constexpr (sizeof(R) == 8)
+    t32 = phase_terms_diff64<R>(t21, t31, (double)qr, k);
+  else
+    t32 = phase_terms_diff<R>(t21, t31);
   P = rfma_t<R>(k.B2, t32.C, p);
   if (GRAD) {
     const R bt = k.B2 * t32.T;
@@ -337,9 +378,7 @@ template <class R, bool GRAD>
 __device__ __forceinline__ void pee_point(const PeeCoef<R>& k, double q, R& P, R dP[4]) {
   pee_accumulate<R, GRAD>(
       k, to_r<R>(q),
-      [&](int i) {
-        return phase_terms<R>((i == 0 ? k.dm21 : i == 1 ? k.dm31 : k.dm32) * q);
-      },
+      [&](int i) { return phase_terms<R>((i == 0 ? k.dm21 : k.dm31) * q); },
       P, dP);
 }
 

@@ -296,8 +296,11 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             const R fw = ok[u] ? f_s[kq] * (R)w_s[rs[u]] : R(0);
             const PhaseTerms<R> t21 = phase_terms<R>(k.dm21 * q);
             const PhaseTerms<R> t31 = phase_terms<R>(k.dm31 * q);
-            const PhaseTerms<R> t32 = sizeof(R) == 4 ? phase_terms_diff<R>(t21, t31)
-                                                     : phase_terms<R>(k.dm32 * q);
+            PhaseTerms<R> t32;
+            if constexpr (sizeof(R) == 8)
+              t32 = phase_terms_diff64<R>(t21, t31, q, k);
+            else
+              t32 = phase_terms_diff<R>(t21, t31);
             sum[0] += fw;
             sum[1] = rfma_t<R>(fw, t21.C, sum[1]);
             sum[2] = rfma_t<R>(fw, t31.C, sum[2]);

@@ -226,6 +226,9 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   for (int i = tid; i < nbp; i += NT) d_s[i] = (i < nb) ? a.data[i] : 0.0;
   for (int i = tid; i < nL; i += NT) w_s[i] = a.wL[i];
   if (sizeof(R) == 4) copy16<NT>(lt_s, a.logtab, (size_t)kLogTab * 16);
+  // The GEMM operand starts at zero (its padding rows and, for shared tiles,
+  // columns kTab..15 stay zero until a per-point tile writes them).
+  for (int i = tid; i < nbp * kScanN; i += NT) bb[i] = R(0);
   __syncthreads();
   // The band is needed only from the smearing on: its copy runs while the
   // point pass computes (issued after the barrier, which would wait for it).
@@ -241,6 +244,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   const int items = a.ppb * nL;
   const int gq = G / nL, gr = G - gq * nL;
 
+  bool bb_clean = true;  // columns kTab..15 of bb are zero (work-group uniform)
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int p_raw = tile * kScanN + n;
     const bool valid = p_raw < a.B;
@@ -321,13 +325,29 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
           for (int c = 0; c < kTab; ++c) sum[c] += __shfl_xor(sum[c], o, kWave);
         }
         if (j < nb && sub == 0) {
+          // Row j of the operand in 16-byte stores (fewer, wider LDS writes
+          // than one per sum: the rows of neighbouring lanes share banks).
+          R* row = bb + j * kScanN;
+          if constexpr (sizeof(R) == 4) {
+            using V4 = float __attribute__((ext_vector_type(4)));
+            using V2 = float __attribute__((ext_vector_type(2)));
+            reinterpret_cast<V4*>(row)[0] = V4{sum[0], sum[1], sum[2], sum[3]};
+            reinterpret_cast<V4*>(row)[1] = V4{sum[4], sum[5], sum[6], sum[7]};
+            reinterpret_cast<V2*>(row)[4] = V2{sum[8], sum[9]};
+          } else {
+            using D2 = double __attribute__((ext_vector_type(2)));
 #pragma unroll
-          for (int c = 0; c < kTab; ++c) bb[j * kScanN + c] = sum[c];
+            for (int c = 0; c < kTab; c += 2) reinterpret_cast<D2*>(row)[c / 2] = D2{sum[c], sum[c + 1]};
+          }
         }
       }
-      // The rest of the GEMM operand: columns kTab..15 and the padded rows.
-      for (int i = tid; i < nbp * kScanN; i += NT)
-        if ((i & (kScanN - 1)) >= kTab || i >= nb * kScanN) bb[i] = R(0);
+      // The rest of the operand (columns kTab..15) is zero unless a per-point
+      // tile of this work-group wrote it.
+      if (!bb_clean) {
+        for (int i = tid; i < nb * kScanN; i += NT)
+          if ((i & (kScanN - 1)) >= kTab) bb[i] = R(0);
+        bb_clean = true;
+      }
     } else {
       // Per-point phases.  The SHARE kernel keeps only mu here and recomputes
       // the tangents in the gradient pass, which keeps its registers for the
@@ -368,6 +388,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         }
         if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
       }
+      bb_clean = false;
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wavefront's band copy
     __syncthreads();

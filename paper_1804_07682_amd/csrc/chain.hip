@@ -14,7 +14,7 @@
 // scope counter, release/acquire fences) adds the chunks in a fixed order and
 // runs the tail.  Results are therefore independent of scheduling.  An
 // uneven batch can instead split the tail off into wide launches over all
-// fits (tail_fwd / tail_adj / tail_final below).
+// fits (tail_fwd / tail_final below).
 //
 // Tail (one work-group per point):
 //   nu_i    = sum_j R_ij mu_j          banded R, one wavefront per 64-row slice
@@ -521,27 +521,28 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bin
 
 // ---- split tail (uneven batches) ------------------------------------------
 // With a split tail the point pass above only writes every fit's bin sums;
-// three more launches finish the chain with the whole GPU on each step, one
-// wavefront per 64-row slice (forward) or 64-column block (adjoint) of every
-// fit, instead of one work-group per fit:
-//   tail_fwd    nu_i, the chi^2 terms and gnu_i of one slice
-//   tail_adj    gmu_j of one column block and its gradient sums
-//   tail_final  per fit: the slice and block partials added in a fixed order
+// two more launches finish the chain with the whole GPU on each step:
+//   tail_fwd    one wavefront per 64-row slice of any fit: nu_i = norm (R mu0)_i,
+//               the chi^2 terms, gnu_i = 2 (1 - d_i / nu_i) and, with the
+//               gradient, the tangent rows (R J0)_ic, all from one pass over
+//               the slice's diagonals; the slice's partials are
+//               sum_i chi2 terms, sum_i gnu_i (R J0)_ic and sum_i gnu_i (R mu0)_i
+//   tail_final  per fit: the slice partials added in a fixed order
+// Carrying the four tangent columns through the smearing replaces the
+// adjoint pass over R^T: sum_j gmu_j J0_jc = sum_i gnu_i (R J0)_ic, so the
+// band is read once per evaluation instead of twice.
 template <class R>
 struct TailArgs {
   const ProbDev* probs;
   const SliceDev* slices;
-  const SliceDev* tslices;    // 64-column blocks of the transposed band
   const int32_t* slice_prob;  // fit of each slice
-  const int32_t* order;       // the launch's items, longest first
-  int64_t n_items;            // slices of all fits (= column blocks)
+  const int32_t* order;       // the launch's slices, longest first
+  int64_t n_items;            // slices of all fits
   int32_t n_fits;
   const R* Rv;
-  const R* RTv;
   const double* data;
   const double* params;
   const R* scratch;
-  R* gnu;                     // [total bins]  d chi2 / d nu
   double* part;               // [n_items][6]  chi2 partial, 5 gradient partials
   double* pred;
   uint32_t* status;
@@ -549,54 +550,73 @@ struct TailArgs {
   double* grad;
 };
 
-constexpr int kTailWaves = 4;    // wavefronts (items) per work-group
-constexpr int kWinDiag = 256;    // diagonals per staged window of mu
+constexpr int kTailWaves = 4;  // wavefronts (slices) per work-group
 
-// acc_l = sum_d B[l][d] v[64 blk + dlo + d + l] for one 64-row block of a
-// band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l), summed
-// over d in ascending order.  v comes from vat(c) for 0 <= c < n and is 0
-// elsewhere; it is staged per wavefront in LDS, kWinDiag diagonals at a time.
-template <class R, class V>
-__device__ __forceinline__ R band_block_dot(const R* __restrict__ Bv, const SliceDev& sd, int blk,
-                                            int lane, int n, R* win, V vat) {
+// Diagonals per staged window.  A gradient window holds five vectors
+// (mu0 and the four tangents), so FP64 halves it to keep a work-group's LDS
+// (and with it the number of resident work-groups) where it was.
+template <class R, bool GRAD>
+constexpr int kWinDiag = (GRAD && sizeof(R) == 8) ? 128 : 256;
+
+// acc[k] = sum_d B[l][d] v_k[64 blk + dlo + d + l], k < NC, for one 64-row
+// block of a band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l),
+// each summed over d in ascending order.  vat(c, k) gives entry c of vector
+// k for 0 <= c < n (the vectors are 0 elsewhere); they are staged
+// per wavefront in LDS ([NC][64 + WD]), WD diagonals at a time.
+template <class R, int NC, int WD, class V>
+__device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const SliceDev& sd,
+                                               int blk, int lane, int n, R* win, V vat,
+                                               R (&acc)[NC]) {
+  constexpr int WS = kSlice + WD;
   const R* bv = Bv + sd.off + lane;
-  R acc = R(0);
-  for (int d0 = 0; d0 < sd.nd; d0 += kWinDiag) {
-    const int d1 = min(sd.nd, d0 + kWinDiag);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = R(0);
+  for (int d0 = 0; d0 < sd.nd; d0 += WD) {
+    const int d1 = min(sd.nd, d0 + WD);
     // Window over the vector entries these diagonals touch: index
     // blk*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1.
     const int cbase = blk * kSlice + sd.dlo + d0;
     const int wn = kSlice + (d1 - d0) - 1;
     for (int w = lane; w < wn; w += kWave) {
       const int c = cbase + w;
-      win[w] = ((unsigned)c < (unsigned)n) ? vat(c) : R(0);
+      const bool in = (unsigned)c < (unsigned)n;
+      // One vector at a time: its loads go out together, and the registers
+      // stay free for the band loads below.
+#pragma unroll 1
+      for (int k = 0; k < NC; ++k) win[k * WS + w] = in ? vat(c, k) : R(0);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const R* wl = win + lane - d0;
     int d = d0;
     for (; d + kTailBatch<R> <= d1; d += kTailBatch<R>) {
-      R x[kTailBatch<R>], y[kTailBatch<R>];
+      // The band loads go out together; the window reads (LDS) follow them.
+      R x[kTailBatch<R>];
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) {
-        x[u] = bv[(int64_t)(d + u) * kSlice];
-        y[u] = win[lane + d + u - d0];
-      }
+      for (int u = 0; u < kTailBatch<R>; ++u) x[u] = bv[(int64_t)(d + u) * kSlice];
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
+      for (int u = 0; u < kTailBatch<R>; ++u)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] = rfma<R>(x[u], wl[k * WS + d + u], acc[k]);
     }
-    for (; d < d1; ++d) acc = rfma<R>(bv[(int64_t)d * kSlice], win[lane + d - d0], acc);
+    for (; d < d1; ++d) {
+      const R x = bv[(int64_t)d * kSlice];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) acc[k] = rfma<R>(x, wl[k * WS + d], acc[k]);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  return acc;
 }
 
-template <class R>
+template <class R, bool GRAD>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
-  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
+  constexpr int NC = GRAD ? 5 : 1;
+  constexpr int WD = kWinDiag<R, GRAD>;
+  __shared__ R win_all[kTailWaves][NC * (kSlice + WD)];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
   const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
   if (idx >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
@@ -606,62 +626,47 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
   const int s = (int)(item - pd.slice_off);
   const int nb = pd.n_bins, C = pd.C;
   const R* sc = a.scratch + pd.scratch_off;
-  const R normr = (R)a.params[5 * (int64_t)f + 4];
-  // nu_i = sum_j R_ij mu_j with mu_j = norm * mu0_j.
-  const R acc = band_block_dot<R>(a.Rv, a.slices[item], s, lane, nb, win_all[wave],
-                                  [&](int c) { return normr * sum_chunks<R>(sc, C, 0, nb, c); });
+  const double norm = a.params[5 * (int64_t)f + 4];
+  // acc[0] = (R mu0)_i and, with the gradient, acc[1 + c] = (R J0)_ic.
+  R acc[NC];
+  band_block_dot<R, NC, WD>(a.Rv, a.slices[item], s, lane, nb, win_all[wave],
+                            [&](int c, int k) { return sum_chunks<R>(sc, C, k, nb, c); }, acc);
   const int i = s * kSlice + lane;
   double chi = 0.0;
+  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   bool badnu = false;
   if (i < nb) {
-    const double nu = (double)acc;
+    const double nu = norm * (double)acc[0];
     const double d = a.data[pd.bin_off + i];
     badnu = !(nu > 0.0) || !isfinite(nu);
     const double ratio = quot_pos(d, nu);
     chi = dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
-    a.gnu[pd.bin_off + i] = (R)(2.0 * (1.0 - ratio));
+    if (GRAD) {
+      const double gn = 2.0 * (1.0 - ratio);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gs[c] = gn * (double)acc[(1 + c) % NC];
+      gs[4] = gn * (double)acc[0];
+    }
     if (a.pred) a.pred[pd.bin_off + i] = nu;
   }
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   chi = wave_sum(chi);
-  if (lane == 0) a.part[item * 6] = chi;
-}
-
-template <class R>
-__global__ void __launch_bounds__(kTailWaves * kWave) tail_adj_kernel(TailArgs<R> a) {
-  __shared__ R win_all[kTailWaves][kSlice + kWinDiag];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
-  if (idx >= a.n_items) return;
-  const int64_t item = a.order[idx];
-  const int f = a.slice_prob[item];
-  const ProbDev pd = a.probs[f];
-  const int cb = (int)(item - pd.slice_off);
-  const int nb = pd.n_bins, C = pd.C;
-  // gmu_j = sum_i R_ij gnu_i, walked along the transposed band.
-  const R* gn = a.gnu + pd.bin_off;
-  const R acc = band_block_dot<R>(a.RTv, a.tslices[item], cb, lane, nb, win_all[wave],
-                                  [&](int c) { return gn[c]; });
-  const int jc = cb * kSlice + lane;
-  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (jc < nb) {
-    const double gmu = (double)acc;
-    const R* sc = a.scratch + pd.scratch_off;
+  if (GRAD) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) gs[c] = gmu * (double)sum_chunks<R>(sc, C, 1 + c, nb, jc);
-    gs[4] = gmu * (double)sum_chunks<R>(sc, C, 0, nb, jc);
+    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
   }
-#pragma unroll
-  for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
   if (lane == 0) {
+    a.part[item * 6] = chi;
+    if (GRAD) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) a.part[item * 6 + 1 + c] = gs[c];
+      for (int c = 0; c < 5; ++c) a.part[item * 6 + 1 + c] = gs[c];
+    }
   }
 }
 
-// One wavefront per fit: lane s takes slice / column block s (a fit has at
-// most kMaxBins / 64 = 64 of them), and the butterfly sums are fixed-order.
+// One wavefront per fit: lane s takes slice s (a fit has at most
+// kMaxBins / 64 = 64 of them), and the butterfly sums are fixed-order.
 template <class R, bool GRAD>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs<R> a) {
   static_assert(kMaxBins <= kSlice * kWave, "one lane per slice");
@@ -698,34 +703,29 @@ int launch_tail(gna_plan* p, const ChainArgs<R>& c, bool grad, hipStream_t s) {
   TailArgs<R> a{};
   a.probs = c.probs;
   a.slices = c.slices;
-  a.tslices = (const SliceDev*)(w + p->lay.tslices);
   a.slice_prob = (const int32_t*)(w + p->lay.slice_prob);
+  a.order = (const int32_t*)(w + p->lay.fwd_order);
   a.n_items = p->total_slices;
   a.n_fits = p->n_points;
   a.Rv = c.Rv;
-  a.RTv = (const R*)(w + p->lay.RTv);
   a.data = c.data;
   a.params = c.params;
   a.scratch = c.scratch;
-  a.gnu = (R*)(w + p->lay.gnu);
   a.part = (double*)(w + p->lay.tailpart);
   a.pred = c.pred;
   a.status = c.status;
   a.chi2 = c.chi2;
   a.grad = c.grad;
   const unsigned g = (unsigned)((a.n_items + kTailWaves - 1) / kTailWaves);
-  a.order = (const int32_t*)(w + p->lay.fwd_order);
-  hipLaunchKernelGGL(tail_fwd_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
-  if (grad) {
-    a.order = (const int32_t*)(w + p->lay.adj_order);
-    hipLaunchKernelGGL(tail_adj_kernel<R>, dim3(g), dim3(kTailWaves * kWave), 0, s, a);
-  }
   const unsigned gf = (unsigned)((a.n_fits + kTailWaves - 1) / kTailWaves);
-  if (grad)
-    hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), dim3(kTailWaves * kWave), 0, s, a);
-  else
-    hipLaunchKernelGGL((tail_final_kernel<R, false>), dim3(gf), dim3(kTailWaves * kWave), 0, s,
-                       a);
+  const dim3 blk(kTailWaves * kWave);
+  if (grad) {
+    hipLaunchKernelGGL((tail_fwd_kernel<R, true>), dim3(g), blk, 0, s, a);
+    hipLaunchKernelGGL((tail_final_kernel<R, true>), dim3(gf), blk, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((tail_fwd_kernel<R, false>), dim3(g), blk, 0, s, a);
+    hipLaunchKernelGGL((tail_final_kernel<R, false>), dim3(gf), blk, 0, s, a);
+  }
   return check_hip(hipGetLastError(), "tail kernel launch");
 }
 

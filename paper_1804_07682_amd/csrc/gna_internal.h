@@ -93,8 +93,7 @@ enum PlanKind { kChain = 0, kFitset = 1 };
 struct Layout {
   size_t probs = 0, slices = 0, slice_prob = 0, tiles = 0, E = 0, f = 0, L = 0, wL = 0,
          edges = 0, data = 0, gl = 0, Rv = 0, scratch = 0, counters = 0, queue = 0, status = 0,
-         Rdense = 0, gnu = 0, tailpart = 0, tslices = 0, RTv = 0, fwd_order = 0, adj_order = 0,
-         total = 0;
+         Rdense = 0, tailpart = 0, fwd_order = 0, total = 0;
 };
 
 struct Shape {
@@ -114,7 +113,6 @@ struct gna_plan {
   int64_t total_bins;
   int64_t total_slices;
   int64_t total_band;     // stored band entries
-  int64_t total_tband;    // fitset: stored entries of the transposed band
   int max_bins;
   int ccap;               // largest chunk count the scratch is sized for
   int64_t tile_capacity;  // fitset: tile-list capacity
@@ -145,9 +143,7 @@ struct gna_plan {
   gna_model model;
   std::vector<gna::ProbDev> probs;     // host copy of the device descriptors
   std::vector<gna::SliceDev> slices;   // host copy
-  std::vector<gna::SliceDev> tslices;  // fitset: 64-column blocks of the transposed band
   std::vector<int32_t> fwd_order;      // fitset: slices, most diagonals first
-  std::vector<int32_t> adj_order;      // fitset: column blocks, most diagonals first
   std::vector<double> edges_host;      // concatenated edges
 };
 

@@ -144,34 +144,6 @@ __global__ void band_kernel(const ProbDev* __restrict__ probs, const SliceDev* _
   }
 }
 
-// Transposed band (uneven batches): block cb holds, for the 64 columns
-// j = 64 cb + l and offsets d' = dlo .. dlo + nd - 1, R[j + d'][j] at
-// off + (d' - dlo) * 64 + l, copied from the band (0 where the band stores
-// nothing), so the adjoint walks R^T exactly as the forward pass walks R.
-template <class R>
-__global__ void transpose_band_kernel(const ProbDev* __restrict__ probs,
-                                      const SliceDev* __restrict__ slices,
-                                      const SliceDev* __restrict__ tslices,
-                                      const int32_t* __restrict__ slice_prob,
-                                      const R* __restrict__ Rv, R* __restrict__ RTv) {
-  const int64_t gb = blockIdx.x;
-  const ProbDev pd = probs[slice_prob[gb]];
-  const SliceDev tb = tslices[gb];
-  const int cb = (int)(gb - pd.slice_off);
-  const int j = cb * kSlice + (int)threadIdx.x;
-  for (int dd = 0; dd < tb.nd; ++dd) {
-    const int i = j + tb.dlo + dd;
-    R v = R(0);
-    if (j < pd.n_bins && i >= 0 && i < pd.n_bins) {
-      const int s = i / kSlice, l = i - (i / kSlice) * kSlice;
-      const SliceDev sd = slices[pd.slice_off + s];
-      const int d = j - i;
-      if (d >= sd.dlo && d < sd.dlo + sd.nd) v = Rv[sd.off + (int64_t)(d - sd.dlo) * kSlice + l];
-    }
-    RTv[tb.off + (int64_t)dd * kSlice + threadIdx.x] = v;
-  }
-}
-
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -541,12 +513,8 @@ void compute_layout(gna_plan* p, PlanBuild& b) {
   L.queue = take(16);
   L.status = take(16);
   L.Rdense = take(p->kind == kChain ? scan_dense_bytes(p) : 0);
-  L.gnu = take(p->kind == kFitset ? rs * p->total_bins : 0);
   L.tailpart = take(p->kind == kFitset ? 6 * 8 * p->total_slices : 0);
-  L.tslices = take(p->kind == kFitset ? sizeof(SliceDev) * p->tslices.size() : 0);
-  L.RTv = take(p->kind == kFitset ? rs * p->total_tband : 0);
   L.fwd_order = take(4 * p->fwd_order.size());
-  L.adj_order = take(4 * p->adj_order.size());
   L.total = off;
 }
 
@@ -611,7 +579,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->share_allowed = (opts && opts->no_shared_phases) ? 0 : 1;
   p->share_phases = p->share_allowed;
   device_limits(p);
-  int64_t pts = 0, bins = 0, edges = 0, Ls = 0, slices = 0, band = 0, tband = 0;
+  int64_t pts = 0, bins = 0, edges = 0, Ls = 0, slices = 0, band = 0;
   for (int i = 0; i < n_probs; ++i) {
     const gna_problem& q = problems[i];
     ProbDev pd{};
@@ -632,29 +600,6 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       b.slice_prob.push_back(i);
     }
     pd.n_slices = (int)(p->slices.size() - s0);
-    if (kind == kFitset) {
-      // Column blocks of the transposed band: the offsets i - j of every
-      // stored entry whose column falls in the block.
-      for (int cb = 0; cb < pd.n_slices; ++cb) {
-        int dmin = 1 << 30, dmax = -(1 << 30);
-        for (int sl = 0; sl < pd.n_slices; ++sl) {
-          const SliceDev& sd = p->slices[s0 + sl];
-          const int lo = std::max(sd.dlo, kSlice * (cb - sl) - (kSlice - 1));
-          const int hi = std::min(sd.dlo + sd.nd - 1, kSlice * (cb - sl) + (kSlice - 1));
-          if (lo <= hi) {
-            dmin = std::min(dmin, lo);
-            dmax = std::max(dmax, hi);
-          }
-        }
-        SliceDev tb{0, 0, tband};
-        if (dmin <= dmax) {
-          tb.dlo = -dmax;
-          tb.nd = dmax - dmin + 1;
-        }
-        tband += (int64_t)tb.nd * kSlice;
-        p->tslices.push_back(tb);
-      }
-    }
     band += nband;
     slices += pd.n_slices;
     pts += (int64_t)q.n_bins * pd.ppb;
@@ -674,18 +619,16 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->total_bins = bins;
   p->total_slices = slices;
   p->total_band = band;
-  p->total_tband = tband;
   if (kind == kFitset) {
-    // Tail work items in longest-first order (each item's cost is its number
-    // of diagonals), so the wide launches do not end on a few long items.
-    auto lpt = [](const std::vector<SliceDev>& v, std::vector<int32_t>& out) {
-      out.resize(v.size());
-      for (size_t i = 0; i < v.size(); ++i) out[i] = (int32_t)i;
-      std::stable_sort(out.begin(), out.end(),
-                       [&](int32_t a, int32_t b) { return v[a].nd > v[b].nd; });
-    };
-    lpt(p->slices, p->fwd_order);
-    lpt(p->tslices, p->adj_order);
+    // Tail work items in longest-first order (each slice's cost is its
+    // number of diagonals), so the wide launch does not end on a few long
+    // slices.
+    const std::vector<SliceDev>& v = p->slices;
+    std::vector<int32_t>& out = p->fwd_order;
+    out.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) out[i] = (int32_t)i;
+    std::stable_sort(out.begin(), out.end(),
+                     [&](int32_t a, int32_t b) { return v[a].nd > v[b].nd; });
   }
   p->edges_host = b.edges;
   // Chunk cap, scratch and tile capacity for every shape the plan may run.
@@ -757,10 +700,7 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
   };
   if ((rc = up(L.slices, p->slices.data(), sizeof(SliceDev) * p->slices.size()))) return rc;
   if ((rc = up(L.slice_prob, b.slice_prob.data(), 4 * b.slice_prob.size()))) return rc;
-  if (p->kind == kFitset &&
-      ((rc = up(L.tslices, p->tslices.data(), sizeof(SliceDev) * p->tslices.size())) ||
-       (rc = up(L.fwd_order, p->fwd_order.data(), 4 * p->fwd_order.size())) ||
-       (rc = up(L.adj_order, p->adj_order.data(), 4 * p->adj_order.size()))))
+  if (p->kind == kFitset && (rc = up(L.fwd_order, p->fwd_order.data(), 4 * p->fwd_order.size())))
     return rc;
   if ((rc = up(L.L, b.L.data(), 8 * b.L.size()))) return rc;
   if ((rc = up(L.wL, b.wL.data(), 8 * b.wL.size()))) return rc;
@@ -799,18 +739,6 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
                        dprobs, dsl, dsp, (const double*)(w + L.edges), p->model.res_a,
                        (float*)(w + L.Rv));
   if ((rc = check_hip(hipGetLastError(), "band_kernel"))) return rc;
-  if (p->kind == kFitset) {
-    const SliceDev* dts = (const SliceDev*)(w + L.tslices);
-    if (p->prec == GNA_FP64)
-      hipLaunchKernelGGL(transpose_band_kernel<double>, dim3((unsigned)p->total_slices),
-                         dim3(kSlice), 0, s, dprobs, dsl, dts, dsp, (const double*)(w + L.Rv),
-                         (double*)(w + L.RTv));
-    else
-      hipLaunchKernelGGL(transpose_band_kernel<float>, dim3((unsigned)p->total_slices),
-                         dim3(kSlice), 0, s, dprobs, dsl, dts, dsp, (const float*)(w + L.Rv),
-                         (float*)(w + L.RTv));
-    if ((rc = check_hip(hipGetLastError(), "transpose_band_kernel"))) return rc;
-  }
   // Counters, queue and status start at zero (a fill kernel, not a memset).
   auto zero = [&](size_t off, int64_t n) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,

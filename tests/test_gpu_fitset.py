@@ -91,15 +91,21 @@ def test_fitset_split_tail_wide_band(prec):
     params = np.array(W.THETA0) * np.array([[1.0] * 5, [1.1, 0.9, 1.0, 1.05, 0.95],
                                             [0.9] * 5, [1.05] * 5])
     chi2, grad = oracle.fitset(problems, MODEL, params, n_threads=8)
+    nu = np.concatenate([oracle.chain(pb, MODEL, th, grad=False, nu=True)["nu"][0]
+                         for pb, th in zip(problems, params)])
+    tc, tg, tp = ((FP64_RTOL, FP64_RTOL, FP64_RTOL) if prec == "fp64" else
+                  (MIXED_CHI2_RTOL, MIXED_GRAD_TOL, MIXED_PRED_RTOL))
     outs = []
     for tail in (1, 2):
         fs, got = _run(problems, params, prec=prec, pred=True, split_tail=tail)
         assert fs.shape()["split_tail"] == tail - 1
-        tc, tg = (FP64_RTOL, FP64_RTOL) if prec == "fp64" else (MIXED_CHI2_RTOL, MIXED_GRAD_TOL)
         assert np.max(rel_err(got["chi2"], chi2)) <= tc
         assert np.max(grad_error(got["grad"], grad, params, chi2)) <= tg
+        assert np.max(rel_err(got["pred"], nu)) <= tp
         outs.append(got["pred"])
-    assert np.max(rel_err(outs[1], outs[0])) <= (1e-13 if prec == "fp64" else 1e-6)
+    # The tails round differently (the split tail scales by norm after the
+    # smearing, in FP64); in mixed precision each is within tp of the oracle.
+    assert np.max(rel_err(outs[1], outs[0])) <= (1e-13 if prec == "fp64" else 2 * tp)
 
 
 def test_fitset_mixed(small_set):

@@ -16,12 +16,15 @@
 // uneven batch can instead split the tail off into wide launches over all
 // fits (tail_fwd / tail_final below).
 //
-// Tail (one work-group per point):
-//   nu_i    = sum_j R_ij mu_j          banded R, one wavefront per 64-row slice
+// Tail (one work-group per point), one pass over the banded R with the
+// tangent columns carried along (one wavefront per 64-row slice):
+//   s_i     = sum_j R_ij mu0_j,  t_ic = sum_j R_ij J0_jc
+//   nu_i    = norm s_i                                      (FP64)
 //   chi2    = 2 sum_i [nu_i - d_i + d_i ln(d_i / nu_i)]     (FP64)
-//   gnu_i   = 2 (1 - d_i / nu_i)                            (FP64, stored in R)
-//   gmu_j   = sum_i R_ij gnu_i         the same band, walked by columns
-//   grad_c  = norm sum_j gmu_j J0_jc,  grad_norm = sum_j gmu_j mu0_j   (FP64 sums)
+//   gnu_i   = 2 (1 - d_i / nu_i)                            (FP64)
+//   grad_c  = norm sum_i gnu_i t_ic,  grad_norm = sum_i gnu_i s_i      (FP64 sums)
+// which equals the adjoint form norm sum_j gmu_j J0_jc with gmu = R^T gnu,
+// without a second pass over R.
 #include <cmath>
 
 #include "gna_internal.h"
@@ -52,102 +55,78 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Dynamic LDS of one work-group (sizes in chain_lds_bytes):
-//   stage [threads][5]        bin sums of a single-tile point
-//   mu    [max_bins]          norm * mu0
-//   gnu   [max_bins]          d chi2 / d nu
-//   part  [split][max_bins]   partial smearing sums of the diagonal chunks
-//                             (absent when split == 1: the forward partials
-//                             then live in gnu, read and overwritten element
-//                             by element, and the adjoint partials in mu,
-//                             which the adjoint no longer reads)
+// Dynamic LDS of one work-group (sizes in chain_lds):
+//   vec   [5][vs]             mu0 and the four J0 columns of the point
+//                             (vs = 0: they stay in the scratch region)
+//   part  [5][threads]        partial smearing sums of the diagonal chunks
+//                             (absent when kf_cap == 1)
 //   red   [waves][6]          per-wave chi2 and gradient partials
 //   flag
 struct TileLds {
   unsigned char* base;
   int threads;
-  int max_bins;
-  int split;
+  int vs;
+  int kf_cap;
   __device__ static size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
   template <class R>
-  __device__ size_t o_mu() const { return align16((size_t)threads * 5 * sizeof(R)); }
-  template <class R>
-  __device__ size_t o_gnu() const { return o_mu<R>() + align16((size_t)max_bins * sizeof(R)); }
-  template <class R>
-  __device__ size_t o_part() const { return o_gnu<R>() + align16((size_t)max_bins * sizeof(R)); }
+  __device__ size_t o_part() const { return align16((size_t)5 * vs * sizeof(R)); }
   template <class R>
   __device__ size_t o_red() const {
-    return o_part<R>() + (split > 1 ? align16((size_t)split * max_bins * sizeof(R)) : 0);
+    return o_part<R>() + (kf_cap > 1 ? align16((size_t)5 * threads * sizeof(R)) : 0);
   }
   template <class R>
-  __device__ R* stage() const { return reinterpret_cast<R*>(base); }
+  __device__ R* vec() const { return reinterpret_cast<R*>(base); }
   template <class R>
-  __device__ R* mu() const { return reinterpret_cast<R*>(base + o_mu<R>()); }
-  template <class R>
-  __device__ R* gnu() const { return reinterpret_cast<R*>(base + o_gnu<R>()); }
-  template <class R>
-  __device__ R* part_fwd() const {
-    return split > 1 ? reinterpret_cast<R*>(base + o_part<R>()) : gnu<R>();
-  }
-  template <class R>
-  __device__ R* part_adj() const {
-    return split > 1 ? reinterpret_cast<R*>(base + o_part<R>()) : mu<R>();
-  }
+  __device__ R* part() const { return reinterpret_cast<R*>(base + o_part<R>()); }
   template <class R>
   __device__ double* red() const { return reinterpret_cast<double*>(base + o_red<R>()); }
   template <class R>
   __device__ int* flag() const { return reinterpret_cast<int*>(red<R>() + (threads / kWave) * 6); }
 };
 
-// gmu_j = sum_i R_ij gnu_i over diagonals d in [d0, d1), for the 64 columns
-// j = 64 cb + lane.  Row i = j - d lies in slice cb - m (lanes >= r) or
-// cb - m - 1 (lanes < r), with d = 64 m + r: every lane is busy and each
-// slice is read as one contiguous segment.  Branch-free body (invalid lanes
-// read element 0 and add 0) so the unrolled loads issue back to back.
+// acc[k] = sum_{d0 <= d < d1} R_{i, i+dlo+d} V[k vst + i + dlo + d], k < NC, for
+// row i = 64 s + lane of one slice of the band (diagonal layout: entry (l, d)
+// at off + (d - dlo) * 64 + l), summed over d in ascending order.  The band
+// stores exact zeros at columns outside [0, nb), which read V at column 0
+// instead (finite), so they add 0.  The band loads of a batch go out together, the
+// vector reads follow them; the last, partial batch is issued the same way
+// (its missing diagonals load nothing and add exact zeros), so a wavefront
+// waits for memory once per batch, not once per diagonal.
 template <class R>
-__device__ R adjoint_range(const R* __restrict__ Rv, const SliceDev* __restrict__ slices, int ns,
-                           int nb, const R* gnus, int cb, int lane, int d0, int d1) {
-  R acc = R(0);
-  int d = d0;
-  while (d < d1) {
-    const int m = d >> 6;  // floor(d / 64)
-    const int dend = min(d1, (m + 1) * kSlice);
-    const int sB = cb - m, sA = cb - m - 1;
-    const bool vB = sB >= 0 && sB < ns, vA = sA >= 0 && sA < ns;
-    const SliceDev zB = vB ? slices[sB] : SliceDev{0, 0, 0};
-    const SliceDev zA = vA ? slices[sA] : SliceDev{0, 0, 0};
-    auto term = [&](int dd, R& rv, R& g) {
-      const int r = dd - m * kSlice;
-      const bool useB = lane >= r;
-      const int s = useB ? sB : sA;
-      const int dlo = useB ? zB.dlo : zA.dlo;
-      const int nd = useB ? zB.nd : zA.nd;
-      const int64_t off = useB ? zB.off : zA.off;
-      const int li = useB ? lane - r : lane + kSlice - r;
-      const int i = s * kSlice + li;
-      const bool ok = (dd >= dlo) && (dd < dlo + nd) && (i < nb);
-      const R x = Rv[ok ? off + (int64_t)(dd - dlo) * kSlice + li : 0];
-      const R y = gnus[ok ? i : 0];
-      rv = ok ? x : R(0);
-      g = y;
-    };
-    // Batches of kTailBatch loads issued together (the barrier keeps the
-    // scheduler from pairing each load with its FMA); same summation order.
-    for (; d + kTailBatch<R> <= dend; d += kTailBatch<R>) {
-      R x[kTailBatch<R>], y[kTailBatch<R>];
+constexpr int kDotBatch = sizeof(R) == 8 ? 8 : 16;
+template <class R, int NC>
+__device__ __forceinline__ void slice_dot(const R* __restrict__ Rv, const SliceDev& sd, int s,
+                                          int lane, int nb, const R* __restrict__ V, int vst,
+                                          int d0, int d1, R (&acc)[NC]) {
+  const R* rv = Rv + sd.off + lane;
+  const int jb = s * kSlice + lane + sd.dlo;  // column of diagonal 0
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) term(d + u, x[u], y[u]);
+  for (int k = 0; k < NC; ++k) acc[k] = R(0);
+  for (int dd = d0; dd < d1; dd += kDotBatch<R>) {
+    R x[kDotBatch<R>];
+#pragma unroll
+    for (int u = 0; u < kDotBatch<R>; ++u)
+      x[u] = (dd + u < d1) ? rv[(int64_t)(dd + u) * kSlice] : R(0);
+    __builtin_amdgcn_sched_barrier(0);
+    // The vector entries of four diagonals are read together, then used:
+    // otherwise each read waits before its FMA.
+#pragma unroll
+    for (int u0 = 0; u0 < kDotBatch<R>; u0 += 4) {
+      R y[4][NC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = jb + dd + u0 + u;
+        const int jc = (unsigned)jj < (unsigned)nb ? jj : 0;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) y[u][k] = V[k * vst + jc];
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
-    }
-    for (; d < dend; ++d) {
-      R x, y;
-      term(d, x, y);
-      acc = rfma<R>(x, y, acc);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] = rfma<R>(x[u0 + u], y[u][k], acc[k]);
     }
   }
-  return acc;
 }
 
 // sum over chunks c < C of sc[(c*5 + comp)*nb + j], added in the order
@@ -303,14 +282,17 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   }
   const int tiles_of_point = pd.n_bin_blocks * pd.C;
   const bool single = (tiles_of_point == 1);
-  R* stage = L.stage<R>();
+  // The point's vectors: in LDS (component k of bin jj at vl[k vs + jj]) when
+  // they fit, else in chunk 0 of the scratch region (sc[k nb + jj]).
+  const bool vlds = L.vs > 0;
+  R* vl = L.vec<R>();
   R* sc = a.scratch + (a.tiles ? pd.scratch_off : (int64_t)td.point * a.scratch_stride);
   if (g == 0 && lb < pd.bins_per_tile && j < nb) {
-    if (single) {
-      stage[lb * 5] = mu;
+    if (single && vlds) {
+      vl[j] = mu;
       if (GRAD) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) stage[lb * 5 + 1 + c] = J[c];
+        for (int c = 0; c < 4; ++c) vl[(1 + c) * L.vs + j] = J[c];
       }
     } else {
       sc[(int64_t)(td.chunk * 5) * nb + j] = mu;
@@ -343,128 +325,113 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   }
 
   // ---- tail ----------------------------------------------------------------
+  constexpr int NC = GRAD ? 5 : 1;
   const int C = pd.C;
-  auto mu0_of = [&](int jj) -> R {
-    return single ? stage[jj * 5] : sum_chunks<R>(sc, C, 0, nb, jj);
-  };
-  auto J0_of = [&](int jj, int cidx) -> R {
-    return single ? stage[jj * 5 + 1 + cidx] : sum_chunks<R>(sc, C, 1 + cidx, nb, jj);
-  };
-  const double norm = th[4];
-  const R normr = (R)norm;
-  R* mus = L.mu<R>();
-  R* gnus = L.gnu<R>();
-  for (int jj = tid; jj < nb; jj += NT) mus[jj] = normr * mu0_of(jj);
+  const double* dat = a.data + pd.bin_off;
+  // This thread's first row of the chi^2 pass below when the slices are
+  // split into chunks (row tid); requested now so that its latency overlaps.
+  const double d_first = (tid < nb) ? dat[tid] : 0.0;
+  // Entries e = c nb + jj of the NC vectors, two per trip so that two
+  // entries' chunk loads are in flight together.
+  if (vlds) {
+    if (!single) {
+#pragma unroll 2
+      for (int e = tid; e < NC * nb; e += NT) {
+        const int c = e / nb, jj = e - (e / nb) * nb;
+        vl[c * L.vs + jj] = sum_chunks<R>(sc, C, c, nb, jj);
+      }
+    }
+  } else if (C > 1) {
+    // In place into chunk 0: each entry is read and written by one thread.
+#pragma unroll 2
+    for (int e = tid; e < NC * nb; e += NT) {
+      const int c = e / nb, jj = e - (e / nb) * nb;
+      const R v = sum_chunks<R>(sc, C, c, nb, jj);
+      sc[c * nb + jj] = v;
+    }
+  }
   __syncthreads();
 
+  const double norm = th[4];
   const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
   const int nwaves = NT / kWave;
   const int ns = pd.n_slices;
   const SliceDev* slices = a.slices + pd.slice_off;
-  const double* dat = a.data + pd.bin_off;
   double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)td.point * nb)
                         : nullptr;
-  R* part = L.part_fwd<R>();
-  const int maxb = L.max_bins;
+  double chi = 0.0;
+  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  bool badnu = false;
+  // Row i (data d) from s_i = acc[0] and t_ic = acc[1 + c].
+  auto finish = [&](int i, double d, const R(&acc)[NC]) {
+    const double nu = norm * (double)acc[0];
+    if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
+    const double ratio = quot_pos(d, nu);
+    chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
+    if (GRAD) {
+      const double gn = 2.0 * (1.0 - ratio);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gs[c] = dfma(gn, (double)acc[(1 + c) % NC], gs[c]);
+      gs[4] = dfma(gn, (double)acc[0], gs[4]);
+    }
+    if (pred) pred[i] = nu;
+  };
 
-  // Forward smearing: work items (slice, chunk of its diagonals) over all waves.
-  const int Kf = min(L.split, max(1, nwaves / ns));
+  // Smearing: work items (slice, chunk of its diagonals) over all waves.  With
+  // one chunk per slice each wavefront finishes its own rows.
+  const int Kf = min(L.kf_cap, max(1, nwaves / ns));
+  const int PS = ns * kSlice;
+  R* part = L.part<R>();  // [Kf][NC][PS]: Kf * PS <= threads
   for (int item = wave; item < ns * Kf; item += nwaves) {
     const int s = item / Kf, kap = item - (item / Kf) * Kf;
     const SliceDev sd = slices[s];
     const int csz = (sd.nd + Kf - 1) / Kf;
-    const int d0 = kap * csz, d1 = min(sd.nd, d0 + csz);
+    const int d0 = min(sd.nd, kap * csz), d1 = min(sd.nd, d0 + csz);
     const int i = s * kSlice + lane;
-    const R* rv = a.Rv + sd.off + lane;
-    auto term = [&](int dd, R& x, R& y) {
-      const int jj = i + sd.dlo + dd;
-      const R m = mus[((unsigned)jj < (unsigned)nb) ? jj : 0];
-      x = rv[(int64_t)dd * kSlice];
-      y = ((unsigned)jj < (unsigned)nb) ? m : R(0);
-    };
-    R acc = R(0);
-    int dd = d0;
-    for (; dd + kTailBatch<R> <= d1; dd += kTailBatch<R>) {
-      R x[kTailBatch<R>], y[kTailBatch<R>];
+    const double di = (Kf == 1 && i < nb) ? dat[i] : 0.0;
+    R acc[NC];
+    if (vlds)
+      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, vl, L.vs, d0, d1, acc);
+    else
+      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, sc, nb, d0, d1, acc);
+    if (i < nb) {
+      if (Kf == 1) {
+        finish(i, di, acc);
+      } else {
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) term(dd + u, x[u], y[u]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) acc = rfma<R>(x[u], y[u], acc);
+        for (int c = 0; c < NC; ++c) part[(kap * NC + c) * PS + i] = acc[c];
+      }
     }
-    for (; dd < d1; ++dd) {
-      R x, y;
-      term(dd, x, y);
-      acc = rfma<R>(x, y, acc);
-    }
-    if (i < nb) part[kap * maxb + i] = acc;
   }
-  __syncthreads();
-  double chi = 0.0;
-  bool badnu = false;
-  for (int i = tid; i < nb; i += NT) {
-    R acc = R(0);
-    for (int kap = 0; kap < Kf; ++kap) acc += part[kap * maxb + i];
-    const double nu = (double)acc;
-    const double d = dat[i];
-    if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-    const double ratio = quot_pos(d, nu);
-    chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
-    gnus[i] = (R)(2.0 * (1.0 - ratio));
-    if (pred) pred[i] = nu;
+  if (Kf > 1) {
+    __syncthreads();
+    for (int i = tid; i < nb; i += NT) {
+      R acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = part[c * PS + i];
+      for (int kap = 1; kap < Kf; ++kap) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += part[(kap * NC + c) * PS + i];
+      }
+      finish(i, i == tid ? d_first : dat[i], acc);
+    }
   }
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   double* red = L.red<R>();
   chi = wave_sum(chi);
-  if (lane == 0) red[wave * 6] = chi;
-  __syncthreads();
-
-  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (GRAD) {
-    part = L.part_adj<R>();
-    // Adjoint smearing: work items (column block, chunk of its diagonals).
-    const int ncb = (nb + kSlice - 1) / kSlice;
-    const int Ka = min(L.split, max(1, nwaves / ncb));
-    for (int item = wave; item < ncb * Ka; item += nwaves) {
-      const int cb = item / Ka, kap = item - (item / Ka) * Ka;
-      int dmin = 1 << 30, dmax = -(1 << 30);
-      for (int s = 0; s < ns; ++s) {
-        const SliceDev sd = slices[s];
-        const int lo = max(sd.dlo, kSlice * (cb - s) - (kSlice - 1));
-        const int hi = min(sd.dlo + sd.nd - 1, kSlice * (cb - s) + (kSlice - 1));
-        if (lo <= hi) {
-          dmin = min(dmin, lo);
-          dmax = max(dmax, hi);
-        }
-      }
-      R acc = R(0);
-      if (dmin <= dmax) {
-        const int span = dmax - dmin + 1;
-        const int csz = (span + Ka - 1) / Ka;
-        const int d0 = dmin + kap * csz, d1 = min(dmax + 1, d0 + csz);
-        acc = adjoint_range<R>(a.Rv, slices, ns, nb, gnus, cb, lane, d0, d1);
-      }
-      const int jc = cb * kSlice + lane;
-      if (jc < nb) part[kap * maxb + jc] = acc;
-    }
-    __syncthreads();
-    for (int jc = tid; jc < nb; jc += NT) {
-      R acc = R(0);
-      for (int kap = 0; kap < Ka; ++kap) acc += part[kap * maxb + jc];
-      const double gmu = (double)acc;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) gs[c] += gmu * (double)J0_of(jc, c);
-      gs[4] += gmu * (double)mu0_of(jc);
-    }
 #pragma unroll
     for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
-    if (lane == 0) {
+  }
+  if (lane == 0) {
+    red[wave * 6] = chi;
+    if (GRAD) {
 #pragma unroll
       for (int c = 0; c < 5; ++c) red[wave * 6 + 1 + c] = gs[c];
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (tid == 0) {
     double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int w = 0; w < nwaves; ++w) {
@@ -488,9 +455,9 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
 }
 
 template <class R, bool GRAD, bool PERSIST, bool SPLIT>
-__global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int max_bins, int split) {
+__global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int vs, int kf_cap) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  TileLds L{lds_raw, (int)blockDim.x, max_bins, split};
+  TileLds L{lds_raw, (int)blockDim.x, vs, kf_cap};
   __shared__ BaseLds bl;
   if (!PERSIST) {
     process_tile<R, GRAD, SPLIT>(a, (int64_t)blockIdx.x, L, bl);
@@ -562,12 +529,13 @@ constexpr int kWinDiag = (GRAD && sizeof(R) == 8) ? 128 : 256;
 // block of a band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l),
 // each summed over d in ascending order.  vat(c, k) gives entry c of vector
 // k for 0 <= c < n (the vectors are 0 elsewhere); they are staged
-// per wavefront in LDS ([NC][64 + WD]), WD diagonals at a time.
+// per wavefront in LDS ([NC][64 + WD + kTailBatch]: a window plus zeros that
+// the last, partial batch of diagonals reads), WD diagonals at a time.
 template <class R, int NC, int WD, class V>
 __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const SliceDev& sd,
                                                int blk, int lane, int n, R* win, V vat,
                                                R (&acc)[NC]) {
-  constexpr int WS = kSlice + WD;
+  constexpr int WS = kSlice + WD + kTailBatch<R>;
   const R* bv = Bv + sd.off + lane;
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc[k] = R(0);
@@ -577,9 +545,9 @@ __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const S
     // blk*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1.
     const int cbase = blk * kSlice + sd.dlo + d0;
     const int wn = kSlice + (d1 - d0) - 1;
-    for (int w = lane; w < wn; w += kWave) {
+    for (int w = lane; w < wn + kTailBatch<R>; w += kWave) {
       const int c = cbase + w;
-      const bool in = (unsigned)c < (unsigned)n;
+      const bool in = w < wn && (unsigned)c < (unsigned)n;
       // One vector at a time: its loads go out together, and the registers
       // stay free for the band loads below.
 #pragma unroll 1
@@ -589,22 +557,19 @@ __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const S
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const R* wl = win + lane - d0;
-    int d = d0;
-    for (; d + kTailBatch<R> <= d1; d += kTailBatch<R>) {
-      // The band loads go out together; the window reads (LDS) follow them.
+    for (int d = d0; d < d1; d += kTailBatch<R>) {
+      // The band loads go out together (the last, partial batch too: its
+      // missing diagonals load nothing and add exact zeros); the window
+      // reads (LDS) follow them.
       R x[kTailBatch<R>];
 #pragma unroll
-      for (int u = 0; u < kTailBatch<R>; ++u) x[u] = bv[(int64_t)(d + u) * kSlice];
+      for (int u = 0; u < kTailBatch<R>; ++u)
+        x[u] = (d + u < d1) ? bv[(int64_t)(d + u) * kSlice] : R(0);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < kTailBatch<R>; ++u)
 #pragma unroll
         for (int k = 0; k < NC; ++k) acc[k] = rfma<R>(x[u], wl[k * WS + d + u], acc[k]);
-    }
-    for (; d < d1; ++d) {
-      const R x = bv[(int64_t)d * kSlice];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) acc[k] = rfma<R>(x, wl[k * WS + d], acc[k]);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -616,7 +581,7 @@ template <class R, bool GRAD>
 __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
   constexpr int NC = GRAD ? 5 : 1;
   constexpr int WD = kWinDiag<R, GRAD>;
-  __shared__ R win_all[kTailWaves][NC * (kSlice + WD)];
+  __shared__ R win_all[kTailWaves][NC * (kSlice + WD + kTailBatch<R>)];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
   const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
   if (idx >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
@@ -752,8 +717,8 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   if (grid > 0x7fffffffLL / sh.threads)
     return fail(GNA_E_UNSUPPORTED, "%lld tiles exceed one launch; use the persistent shape",
                 (long long)grid);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lds, s, a, p->max_bins,
-                     chain_split(p, sh));
+  const ChainLds cl = chain_lds(p, sh);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lds, s, a, cl.vs, cl.kf_cap);
   return check_hip(hipGetLastError(), "chain_kernel launch");
 }
 

@@ -164,8 +164,15 @@ int launch_scan(gna_plan* p, const double* params, int32_t B, double* chi2, doub
 int build_scan_tables(gna_plan* p, hipStream_t s);
 bool scan_supported(const gna_plan* p);
 size_t scan_dense_bytes(const gna_plan* p);
+// Dynamic LDS of the generic kernel: vs = LDS stride of the point's vectors
+// (0: they stay in the scratch region), kf_cap = largest number of diagonal
+// chunks per slice, bytes = total.
+struct ChainLds {
+  int vs = 0, kf_cap = 1;
+  size_t bytes = 0;
+};
+ChainLds chain_lds(const gna_plan* p, const Shape& sh);
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
-int chain_split(const gna_plan* p, const Shape& sh);
 // Sets the per-problem tiling of `sh` (and, for a fitset, rebuilds and
 // uploads the tile list when the plan has a workspace).
 int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s);

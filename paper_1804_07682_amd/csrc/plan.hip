@@ -280,35 +280,27 @@ int64_t build_slices(const double* e, int nb, double res_a, std::vector<SliceDev
 // ---------------------------------------------------------------------------
 // Launch shapes.
 // ---------------------------------------------------------------------------
-// LDS of the generic kernel without the chunk partials.
-static size_t chain_lds_base(const gna_plan* p, const Shape& sh) {
+// LDS of the generic kernel's tail: the point's five vectors when they fit
+// the budget (else they stay in the scratch region), then the partial sums
+// of up to eight diagonal chunks per slice when those fit too (a chunk of
+// each slice per wavefront: at most 5 x threads values), and the per-wave
+// reduction slots and flag.
+ChainLds chain_lds(const gna_plan* p, const Shape& sh) {
   const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  size_t b = align_up((size_t)sh.threads * 5 * rs, 16);  // per-tile bin sums
-  b += align_up((size_t)p->max_bins * rs, 16);           // mu
-  b += align_up((size_t)p->max_bins * rs, 16);           // d chi2 / d nu
-  b += align_up((size_t)(sh.threads / kWave) * 6 * 8, 16);
-  b += 16;  // flags
-  return b;
-}
-
-// Number of diagonal chunks the smearing of one slice may be split into: each
-// chunk's partial sums take max_bins values of LDS.  With one chunk no
-// partial buffer is needed (the kernel reuses the mu and gnu arrays).
-int chain_split(const gna_plan* p, const Shape& sh) {
-  const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  const size_t base = chain_lds_base(p, sh);
-  if (base >= p->lds_limit) return 1;
-  const size_t room = (p->lds_limit - base) / ((size_t)p->max_bins * rs);
-  const int split = (int)std::min<size_t>({8, (size_t)(sh.threads / kWave), room});
-  return split >= 2 ? split : 1;
+  const size_t red = align_up((size_t)(sh.threads / kWave) * 6 * 8, 16) + 16;
+  const size_t vec = align_up((size_t)5 * p->max_bins * rs, 16);
+  const size_t part = align_up((size_t)5 * sh.threads * rs, 16);
+  ChainLds c;
+  c.vs = (vec + red <= p->lds_limit) ? p->max_bins : 0;
+  const size_t base = (c.vs ? vec : 0) + red;
+  c.kf_cap = (base + part <= p->lds_limit) ? 8 : 1;
+  c.bytes = base + (c.kf_cap > 1 ? part : 0);
+  return c;
 }
 
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
   if (sh.split) return 0;  // the point pass alone keeps nothing in LDS
-  const size_t rs = (p->prec == GNA_FP64) ? 8 : 4;
-  const int split = chain_split(p, sh);
-  const size_t part = split > 1 ? align_up((size_t)split * p->max_bins * rs, 16) : 0;
-  return chain_lds_base(p, sh) + part;
+  return chain_lds(p, sh).bytes;
 }
 
 namespace {

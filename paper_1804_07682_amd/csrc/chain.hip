@@ -527,14 +527,15 @@ constexpr int kWinDiag = (GRAD && sizeof(R) == 8) ? 128 : 256;
 
 // acc[k] = sum_d B[l][d] v_k[64 blk + dlo + d + l], k < NC, for one 64-row
 // block of a band in diagonal layout (entry (l, d) at off + (d - dlo) * 64 + l),
-// each summed over d in ascending order.  vat(c, k) gives entry c of vector
-// k for 0 <= c < n (the vectors are 0 elsewhere); they are staged
+// each summed over d in ascending order.  Entry c of vector k (0 <= c < n;
+// the vectors are 0 elsewhere) is the sum of the C chunk partials
+// sc[(chunk*5 + k)*n + c]; the entries are staged
 // per wavefront in LDS ([NC][64 + WD + kTailBatch]: a window plus zeros that
 // the last, partial batch of diagonals reads), WD diagonals at a time.
-template <class R, int NC, int WD, class V>
+template <class R, int NC, int WD>
 __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const SliceDev& sd,
-                                               int blk, int lane, int n, R* win, V vat,
-                                               R (&acc)[NC]) {
+                                               int blk, int lane, int n, R* win,
+                                               const R* __restrict__ sc, int C, R (&acc)[NC]) {
   constexpr int WS = kSlice + WD + kTailBatch<R>;
   const R* bv = Bv + sd.off + lane;
 #pragma unroll
@@ -545,13 +546,27 @@ __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const S
     // blk*64 + dlo + d0 + w, w < 64 + (d1 - d0) - 1.
     const int cbase = blk * kSlice + sd.dlo + d0;
     const int wn = kSlice + (d1 - d0) - 1;
-    for (int w = lane; w < wn + kTailBatch<R>; w += kWave) {
-      const int c = cbase + w;
-      const bool in = w < wn && (unsigned)c < (unsigned)n;
-      // One vector at a time: its loads go out together, and the registers
-      // stay free for the band loads below.
+    if (C == 1) {
+      // One chunk: the entries are plain loads, all of two trips in flight.
+#pragma unroll 2
+      for (int w = lane; w < wn + kTailBatch<R>; w += kWave) {
+        const int c = cbase + w;
+        const bool in = w < wn && (unsigned)c < (unsigned)n;
+        R v[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) v[k] = in ? sc[(int64_t)k * n + c] : R(0);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) win[k * WS + w] = v[k];
+      }
+    } else {
+      for (int w = lane; w < wn + kTailBatch<R>; w += kWave) {
+        const int c = cbase + w;
+        const bool in = w < wn && (unsigned)c < (unsigned)n;
+        // One vector at a time: its chunk loads go out together, and the
+        // registers stay free for the band loads below.
 #pragma unroll 1
-      for (int k = 0; k < NC; ++k) win[k * WS + w] = in ? vat(c, k) : R(0);
+        for (int k = 0; k < NC; ++k) win[k * WS + w] = in ? sum_chunks<R>(sc, C, k, n, c) : R(0);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -594,8 +609,7 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
   const double norm = a.params[5 * (int64_t)f + 4];
   // acc[0] = (R mu0)_i and, with the gradient, acc[1 + c] = (R J0)_ic.
   R acc[NC];
-  band_block_dot<R, NC, WD>(a.Rv, a.slices[item], s, lane, nb, win_all[wave],
-                            [&](int c, int k) { return sum_chunks<R>(sc, C, k, nb, c); }, acc);
+  band_block_dot<R, NC, WD>(a.Rv, a.slices[item], s, lane, nb, win_all[wave], sc, C, acc);
   const int i = s * kSlice + lane;
   double chi = 0.0;
   double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};

@@ -263,3 +263,35 @@ def test_autograd_gradcheck_mini_config(mfma):
     u = torch.zeros_like(th0, requires_grad=True)
     assert torch.autograd.gradcheck(lambda u: gna.chi2(th0 * (1 + u), plan), (u,), eps=1e-6,
                                     atol=1e-6, rtol=1e-4)
+
+
+@pytest.fixture(scope="module")
+def wide():
+    """4000 bins (near the 4096 limit), GL order 2, one baseline: the five
+    vectors of the tail (5 x 4000 values) exceed the LDS budget in both
+    precisions, so the tail reads them from the scratch region."""
+    pr = with_data(W.problem(W.uniform_edges(4000), 2, [52.5]), MODEL, W.SEED + 7)
+    P = np.atleast_2d(THETAS[1])
+    return pr, P, oracle.chain(pr, MODEL, P, grad=True, nu=True)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(threads=256, lanes_per_bin=1, chunks=1),  # 16 bin blocks, one chunk each
+    dict(threads=512, lanes_per_bin=2, chunks=3),  # chunk sums reduced in place
+    dict(threads=1024, lanes_per_bin=4, chunks=2, persistent=1),
+])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_wide_chain_vectors_in_scratch(wide, opts, prec):
+    pr, P, ref = wide
+    plan = _plan(pr, prec=prec, smear_mfma=0, **opts)
+    for _ in range(2):  # the in-place chunk sums are rebuilt by every launch
+        got = _eval(plan, P)
+        if prec == "fp64":
+            _check_fp64(got, ref, P)
+        else:
+            # FP32 smearing sums over up to ~340 diagonals: the uneven-batch
+            # bounds of the wide-band fits.
+            assert np.max(rel_err(got["pred"], ref["nu"])) <= 1e-5
+            assert np.max(rel_err(got["chi2"], ref["chi2"])) <= 1e-4
+            assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= 1e-3
+    assert plan.status() == 0

@@ -222,12 +222,11 @@ typedef struct gna_problem {
  *                  neighbours.  1: every point evaluates its own phases, and
  *                  its result does not depend on the rest of the batch.
  *   split_tail     (fitset plans only) 0: automatic; 1: each fit's tail
- *                  (smearing, chi^2, adjoint) runs in the work-group that
+ *                  (smearing, chi^2, gradient) runs in the work-group that
  *                  finishes the fit's last tile; 2: the point pass only
- *                  stores bin sums, and three more launches run the tails of
- *                  all fits with one wavefront per 64-row slice (forward) and
- *                  per 64-column block (adjoint), then add each fit's
- *                  partials in a fixed order.
+ *                  stores bin sums, and two more launches run the tails of
+ *                  all fits with one wavefront per 64-row slice, then add
+ *                  each fit's partials in a fixed order.
  */
 typedef struct gna_launch_opts {
   int32_t threads;

@@ -518,7 +518,7 @@ def main():
     global TUNE
     TUNE = not args.no_tune
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the design notes describe how the scan would shard).", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 #define GNA_E_DOMAIN (-2)      /* a device-side domain error was latched (see below)     */
 #define GNA_E_HIP (-3)         /* a HIP runtime call failed (message names it)           */
 #define GNA_E_WORKSPACE (-4)   /* workspace missing, misaligned or too small              */
-#define GNA_E_UNSUPPORTED (-5) /* valid request outside what this build implements        */
+#define GNA_E_UNSUPPORTED (-5) /* valid request outside what this library implements      */
 
 /* ---- precision modes ----------------------------------------------------- */
 /* GNA_FP64: every step in FP64.

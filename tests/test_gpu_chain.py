@@ -295,3 +295,28 @@ def test_wide_chain_vectors_in_scratch(wide, opts, prec):
             assert np.max(rel_err(got["chi2"], ref["chi2"])) <= 1e-4
             assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= 1e-3
     assert plan.status() == 0
+
+
+@pytest.mark.parametrize("opts", [
+    dict(threads=512, lanes_per_bin=1, chunks=1),   # one tile; slices split into diagonal chunks
+    dict(threads=128, lanes_per_bin=2, chunks=3),   # hand-off; one chunk per slice
+])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_chain_without_gradient(cfg0, opts, prec):
+    """chi^2 and the prediction without the gradient (the tail carries mu0
+    alone), against the oracle and against the same plan's gradient launch."""
+    P = np.atleast_2d(THETAS[1])
+    plan = _plan(cfg0, prec=prec, smear_mfma=0, **opts)
+    Pt = torch.tensor(P, dtype=torch.float64, device=DEV)
+    out = plan.eval(Pt, grad=False, pred=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    with_grad = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=False, nu=True)
+    tp, tc = (FP64_RTOL, FP64_RTOL) if prec == "fp64" else (MIXED_PRED_RTOL, MIXED_CHI2_RTOL)
+    assert np.max(rel_err(got["pred"], ref["nu"])) <= tp
+    assert np.max(rel_err(got["chi2"], ref["chi2"])) <= tc
+    # The same sums in the same order: bit-identical to the gradient launch.
+    assert np.array_equal(got["chi2"], with_grad["chi2"])
+    assert np.array_equal(got["pred"], with_grad["pred"])
+    assert plan.status() == 0

@@ -49,6 +49,20 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def _baselines(L, wL):
+    """Baselines and their weights as contiguous float64 arrays (wL may be None);
+    the library reads n_L weights, so a weight vector of another length is refused."""
+    L = _f64(np.atleast_1d(L))
+    if L.ndim != 1:
+        raise ValueError("L must be a 1-D sequence of baselines")
+    if wL is None:
+        return L, None
+    w = _f64(np.atleast_1d(wL))
+    if w.shape != L.shape:
+        raise ValueError(f"wL has {w.size} weights for {L.size} baselines")
+    return L, w
+
+
 def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float64):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
@@ -56,6 +70,13 @@ def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float64):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _theta4(theta):
+    th = _f64(theta).ravel()
+    if th.size < 4:
+        raise ValueError("theta needs (dm2_21, dm2_31, s12, s13)")
+    return th[:4].copy()
 
 
 def abi_version() -> int:
@@ -75,10 +96,13 @@ def make_model(model: dict) -> Model:
 
 def make_problem(problem: dict, keep: list) -> Problem:
     edges = _f64(problem["edges"])
-    L = _f64(np.atleast_1d(problem["L"]))
-    wL = None if problem.get("wL") is None else _f64(problem["wL"])
+    if edges.ndim != 1 or edges.size < 2:
+        raise ValueError("edges must be a 1-D sequence of at least 2 values")
+    L, wL = _baselines(problem["L"], problem.get("wL"))
     nb = edges.size - 1
     data = _f64(problem["data"]) if problem.get("data") is not None else np.zeros(nb)
+    if data.shape != (nb,):
+        raise ValueError(f"data has {data.size} values for {nb} bins")
     keep.extend([edges, L, wL, data])
     p = Problem()
     p.n_bins = nb
@@ -115,9 +139,8 @@ def gna_pee(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Tensor |
     """
     _need_cuda(E, "E")
     pr = _prec(prec)
-    L = _f64(np.atleast_1d(L))
-    wLa = None if wL is None else _f64(wL)
-    th = _f64(theta)[:4].copy()
+    L, wLa = _baselines(L, wL)
+    th = _theta4(theta)
     odt = torch.float64 if pr == GNA_FP64 else torch.float32
     if out is None:
         out = torch.empty(E.numel(), dtype=odt, device=E.device)
@@ -142,15 +165,21 @@ def gna_prob(E: torch.Tensor, alpha, beta, L, angles, dm2, wL=None, antineutrino
     """
     _need_cuda(E, "E")
     pr = _prec(prec)
-    L = _f64(np.atleast_1d(L))
-    wLa = None if wL is None else _f64(wL)
-    ang = _f64(angles)[:4].copy()
-    dm = _f64(dm2)[:2].copy()
+    L, wLa = _baselines(L, wL)
+    ang = _f64(angles).ravel()
+    dm = _f64(dm2).ravel()
+    if ang.size < 4 or dm.size < 2:
+        raise ValueError("angles needs 4 values and dm2 needs 2")
+    ang, dm = ang[:4].copy(), dm[:2].copy()
+    if alpha not in FLAVOURS or beta not in FLAVOURS:
+        raise ValueError("flavours are 'e', 'mu', 'tau' (or 0, 1, 2)")
     odt = torch.float64 if pr == GNA_FP64 else torch.float32
     if out is None:
         out = torch.empty(E.numel(), dtype=odt, device=E.device)
     else:
         _need_cuda(out, "out", odt)
+        if out.numel() != E.numel():
+            raise ValueError("out has the wrong size")
     check(load().gna_prob(_ptr(E), E.numel(), FLAVOURS[alpha], FLAVOURS[beta], L.size, _dptr(L),
                           _dptr(wLa), _dptr(ang), _dptr(dm), int(bool(antineutrino)), _ptr(out),
                           pr, _stream(E.device)), "gna_prob")
@@ -170,9 +199,8 @@ def gna_pee_host(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Ten
             or not E.is_contiguous():
         raise TypeError("E must be a contiguous CPU float64 tensor")
     pr = _prec(prec)
-    L = _f64(np.atleast_1d(L))
-    wLa = None if wL is None else _f64(wL)
-    th = _f64(theta)[:4].copy()
+    L, wLa = _baselines(L, wL)
+    th = _theta4(theta)
     odt = torch.float64 if pr == GNA_FP64 else torch.float32
     n = E.numel()
     if out is None:

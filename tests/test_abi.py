@@ -161,3 +161,23 @@ def test_pee_host_sizing_and_validation(lib):
     assert call(ws_bytes=100) == -4            # workspace too small
     assert call(chunk=3) == -1                 # odd chunk
     assert call(th_=np.array([7.5e-5, 2.5e-3, 1.3, 0.02])) == -1  # s12 outside [0, 1]
+
+
+def test_binding_rejects_short_host_arrays(lib):
+    """The C side reads n_L weights and n_bins data values: the binding refuses
+    vectors of any other length before the call (no GPU needed)."""
+    from paper_1804_07682_amd import api
+    pr = W.config0()
+    pr["data"] = np.ones(240)
+    keep = []
+    api.make_problem(pr, keep)  # well-formed
+    with pytest.raises(ValueError, match="data"):
+        api.make_problem(dict(pr, data=np.ones(239)), keep)
+    with pytest.raises(ValueError, match="wL"):
+        api.make_problem(dict(pr, L=[50.0, 55.0], wL=[1.0]), keep)
+    with pytest.raises(ValueError, match="wL"):
+        api._baselines([52.5], [0.5, 0.5])
+    L, w = api._baselines(52.5, None)
+    assert L.shape == (1,) and w is None
+    with pytest.raises(ValueError, match="theta"):
+        api._theta4([7.5e-5, 2.5e-3, 0.3])

@@ -80,3 +80,32 @@ def test_prob_mixed_and_baselines():
     ref = sum(wr * oracle.prob_general(0, 1, E, Lr, DM[0], DM[1], *ang) for wr, Lr in zip(w, L))
     assert np.max(np.abs(_gpu(E, "e", "mu", L, ang, wL=w) - ref)) <= 1e-12
     assert np.max(np.abs(_gpu(E, "e", "mu", L, ang, wL=w, prec="mixed") - ref)) <= 2e-6
+
+
+def test_prob_cp_odd_part_on_gpu():
+    """P(delta) - P(-delta) for e -> mu against the Jarlskog closed form
+    16 J sin D21 sin D32 sin D31 (PDG convention), independent of the oracle."""
+    E = W.config1_energies(20_001) * 0.4
+    L = 810.0
+    th12, th13, th23, dcp = 0.7, 0.3, 0.9, -2.0
+    dm = (7.5e-4, 2.5e-3)
+    import paper_1804_07682_amd as gna
+    Et = torch.from_numpy(E).to(DEV)
+    Pp = gna.gna_prob(Et, "e", "mu", L, (th12, th13, th23, dcp), dm).cpu().numpy()
+    Pm = gna.gna_prob(Et, "e", "mu", L, (th12, th13, th23, -dcp), dm).cpu().numpy()
+    J = (math.sin(2 * th12) * math.sin(2 * th23) * math.sin(2 * th13) * math.cos(th13)
+         * math.sin(dcp) / 8)
+    q = 1266.9326794198487 * L / E
+    ref = 16 * J * np.sin(dm[0] * q) * np.sin((dm[1] - dm[0]) * q) * np.sin(dm[1] * q)
+    assert np.max(np.abs(ref)) > 0.05
+    assert np.max(np.abs((Pp - Pm) - ref)) <= 2e-12
+
+
+def test_prob_rejects_wrong_output_size():
+    import paper_1804_07682_amd as gna
+    E = torch.from_numpy(W.config1_energies(1001)).to(DEV)
+    with pytest.raises(ValueError, match="size"):
+        gna.gna_prob(E, "e", "mu", 295.0, ANGLES[0], DM,
+                     out=torch.empty(1000, dtype=torch.float64, device=DEV))
+    with pytest.raises(ValueError, match="wL"):
+        gna.gna_prob(E, "e", "mu", [295.0, 810.0], ANGLES[0], DM, wL=[1.0])

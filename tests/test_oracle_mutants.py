@@ -52,6 +52,20 @@ MUTANTS = {
     "phase constant off in the 5th digit":
         ("constexpr double K_PHASE = 1266.9326794198487;",
          "constexpr double K_PHASE = 1266.9426794198487;"),
+    "spectrum quadratic term linear in E":
+        ("std::exp(a[0] + a[1] * E + a[2] * E * E + a[3] * E * E * E)",
+         "std::exp(a[0] + a[1] * E + a[2] * E + a[3] * E * E * E)"),
+    "spectrum cubic term quadratic in E":
+        ("std::exp(a[0] + a[1] * E + a[2] * E * E + a[3] * E * E * E)",
+         "std::exp(a[0] + a[1] * E + a[2] * E * E + a[3] * E * E)"),
+    "spectrum constant term dropped":
+        ("std::exp(a[0] + a[1] * E + a[2] * E * E + a[3] * E * E * E)",
+         "std::exp(a[1] * E + a[2] * E * E + a[3] * E * E * E)"),
+    "CP phase of the mixing matrix with the opposite sign":
+        ("const cplx eid = std::polar(1.0, dcp);   // e^{+i delta}\n"
+         "  const cplx emid = std::polar(1.0, -dcp); // e^{-i delta}",
+         "const cplx eid = std::polar(1.0, -dcp);\n"
+         "  const cplx emid = std::polar(1.0, dcp);"),
     "baseline weight ignored":
         ("acc += wr * pee_point<double>(E[i], L[r], theta[0], theta[1], theta[2], theta[3]);",
          "acc += pee_point<double>(E[i], L[r], theta[0], theta[1], theta[2], theta[3]);"),

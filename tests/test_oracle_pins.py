@@ -89,6 +89,34 @@ def test_general_formula_matches_amplitude_form(L):
                 np.testing.assert_allclose(g, x, rtol=0, atol=2e-12)
 
 
+def test_cp_odd_part_against_jarlskog_closed_form():
+    """Pins the sign convention of delta_CP in the mixing matrix (Sec. 4.1's Im
+    term is odd in delta; unitarity and the amplitude form are blind to
+    delta -> -delta).  In the three-angle, one-phase parametrisation with
+    U_e3 = sin th13 e^{-i delta}, the Jarlskog invariant is
+    J = sin 2th12 sin 2th23 sin 2th13 cos th13 sin delta / 8, and for e -> mu
+    the Im terms add up to 8 J sin D21 sin D32 sin D31 (D_ij = dm2_ij L / 4E;
+    sin 2a + sin 2b - sin 2(a + b) = 4 sin a sin b sin(a + b) with
+    D31 = D21 + D32), so P(delta) - P(-delta) = 16 J sin D21 sin D32 sin D31."""
+    K = oracle.phase_constant()
+    E = np.linspace(0.3, 5.0, 400)
+    cases = [(295.0, 0.59, 0.15, 0.78, 1.2), (810.0, 0.7, 0.3, 0.9, -2.0),
+             (1300.0, 0.5, 0.4, 0.6, 2.6)]
+    for L, th12, th13, th23, dcp in cases:
+        dm21, dm31 = 7.5e-4, 2.5e-3
+        Pp = oracle.prob_general(0, 1, E, L, dm21, dm31, th12, th13, th23, dcp)
+        Pm = oracle.prob_general(0, 1, E, L, dm21, dm31, th12, th13, th23, -dcp)
+        J = (math.sin(2 * th12) * math.sin(2 * th23) * math.sin(2 * th13) * math.cos(th13)
+             * math.sin(dcp) / 8)
+        q = K * L / E
+        d21, d31 = dm21 * q, dm31 * q
+        ref = 16 * J * np.sin(d21) * np.sin(d31 - d21) * np.sin(d31)
+        assert np.max(np.abs(ref)) > 0.05  # the CP-odd part is large here
+        np.testing.assert_allclose(Pp - Pm, ref, rtol=0, atol=2e-12)
+        # CP-even part: the same for both signs of delta up to the CP-odd term.
+        np.testing.assert_allclose(Pp + Pm, 2 * Pp - ref, rtol=0, atol=4e-12)
+
+
 def test_unitarity_rows_and_columns():
     rng = np.random.default_rng(11)
     for _ in range(10):
@@ -249,6 +277,91 @@ def test_flux_xsec_closed_form_integral():
     # Bin 0 straddles the threshold (1.804 MeV): the integrand has a sqrt kink,
     # so the rule converges slowly there, but the sign and size are right.
     assert 0 < mu[0] < exact[0] * 1.05
+
+
+# Spectrum pins: with m_e = 0 the cross section is (E - delta)^2 above
+# E = delta, the baseline L = 0 gives P = 1 and norm = 1, so mu_j is
+# N0 int_bin S(E) (E - delta)^2 dE.  Each coefficient of the exponent's
+# polynomial is pinned by an integral computed from a closed form or series
+# of its own (mpmath), never by evaluating S at the quadrature points.
+SPEC_EDGES = W.uniform_edges(60)
+
+
+def _spectrum_mu(spec):
+    m = W.model(spec=spec, m_e=0.0)
+    pr = W.problem(SPEC_EDGES, 10, [0.0])
+    pr["data"] = np.ones(60)
+    return m, oracle.chain(pr, m, TH, grad=False, mu=True)["mu"][0]
+
+
+def test_spectrum_linear_exponent_closed_form():
+    """S = exp(a0 + a1 E): int e^{a1 E} x^2 dE = e^{a1 E} (x^2/a1 - 2x/a1^2 + 2/a1^3),
+    x = E - delta."""
+    a0, a1 = 0.3, -0.25
+    m, mu = _spectrum_mu((a0, a1, 0.0, 0.0))
+    mp.mp.dps = 40
+    d, A1 = mp.mpf(m["xsec_delta"]), mp.mpf(a1)
+
+    def F(E):
+        x = mp.mpf(E) - d
+        return mp.exp(A1 * mp.mpf(E)) * (x * x / A1 - 2 * x / A1 ** 2 + 2 / A1 ** 3)
+
+    ref = [float(m["n0"] * mp.exp(mp.mpf(a0)) * (F(SPEC_EDGES[j + 1]) - F(SPEC_EDGES[j])))
+           for j in range(60)]
+    np.testing.assert_allclose(mu, ref, rtol=1e-13, atol=0)
+
+
+def test_spectrum_quadratic_exponent_closed_form():
+    """S = exp(a1 E + a2 E^2), a2 = -alpha < 0: completing the square,
+    S = exp(a1^2 / (4 alpha)) exp(-alpha u^2), u = E - c, c = a1 / (2 alpha), and
+    int (u + b)^2 e^{-alpha u^2} du (b = c - delta) in terms of erf:
+      -u e/(2 alpha) + sqrt(pi) erf(sqrt(alpha) u) / (4 alpha^{3/2})
+      - b e/alpha + b^2 sqrt(pi) erf(sqrt(alpha) u) / (2 sqrt(alpha)),  e = e^{-alpha u^2}."""
+    a1, a2 = -0.25, -0.06
+    m, mu = _spectrum_mu((0.0, a1, a2, 0.0))
+    mp.mp.dps = 40
+    al = -mp.mpf(a2)
+    c = mp.mpf(a1) / (2 * al)
+    b = c - mp.mpf(m["xsec_delta"])
+    sa = mp.sqrt(al)
+
+    def F(E):
+        u = mp.mpf(E) - c
+        e = mp.exp(-al * u * u)
+        er = mp.erf(sa * u)
+        return (-u * e / (2 * al) + mp.sqrt(mp.pi) * er / (4 * al * sa) - b * e / al
+                + b * b * mp.sqrt(mp.pi) * er / (2 * sa))
+
+    pref = mp.mpf(m["n0"]) * mp.exp(mp.mpf(a1) ** 2 / (4 * al))
+    ref = [float(pref * (F(SPEC_EDGES[j + 1]) - F(SPEC_EDGES[j]))) for j in range(60)]
+    np.testing.assert_allclose(mu, ref, rtol=1e-13, atol=0)
+
+
+def test_spectrum_cubic_exponent_series():
+    """S = exp(a1 E + a3 E^3): expand exp(a3 E^3) = sum_n (a3 E^3)^n / n!; each
+    term is int E^k e^{-alpha E} dE = alpha^{-(k+1)} (incomplete gamma of k + 1
+    between alpha e_j and alpha e_{j+1}), alpha = -a1; |a3 E^3| <= 2.6 on the
+    axis, so 45 terms leave < 1e-25 relative."""
+    a1, a3 = -0.25, 0.0015
+    m, mu = _spectrum_mu((0.0, a1, 0.0, a3))
+    mp.mp.dps = 40
+    al = -mp.mpf(a1)
+    d = mp.mpf(m["xsec_delta"])
+    A3 = mp.mpf(a3)
+
+    def moment(k, lo, hi):
+        return mp.gammainc(k + 1, al * lo, al * hi) / al ** (k + 1)
+
+    ref = []
+    for j in range(60):
+        lo, hi = mp.mpf(SPEC_EDGES[j]), mp.mpf(SPEC_EDGES[j + 1])
+        acc = mp.mpf(0)
+        for n in range(45):
+            k = 3 * n
+            term = moment(k + 2, lo, hi) - 2 * d * moment(k + 1, lo, hi) + d * d * moment(k, lo, hi)
+            acc += A3 ** n / mp.factorial(n) * term
+        ref.append(float(mp.mpf(m["n0"]) * acc))
+    np.testing.assert_allclose(mu, ref, rtol=1e-13, atol=0)
 
 
 def test_flux_xsec_pieces():

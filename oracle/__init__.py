@@ -71,9 +71,14 @@ def _load():
     lib.oracle_chain.argtypes = [C.POINTER(_Desc), i32, _dp, _dp, _dp, _dp, _dp, i32]
     lib.oracle_fitset.argtypes = [i32, C.POINTER(_Desc), _dp, _dp, _dp, i32]
     lib.oracle_chi2_complex_step.argtypes = [C.POINTER(_Desc), _dp, _dp, _dp]
+    lib.oracle_bin_integrate.argtypes = [i64, i32, i32, _dp, _dp, _dp]
+    lib.oracle_smear_apply.argtypes = [i32, i32, _dp, i32, i64, _dp, _dp]
+    lib.oracle_chi2.argtypes = [i32, i64, _dp, _dp, i64, _dp, _dp]
+    lib.oracle_chi2_dnu_complex_step.argtypes = [i32, _dp, _dp, _dp, _dp]
     for name in ("oracle_pee", "oracle_gauss_legendre", "oracle_quadrature",
                  "oracle_flux_xsec", "oracle_smearing", "oracle_chain", "oracle_fitset",
-                 "oracle_chi2_complex_step"):
+                 "oracle_chi2_complex_step", "oracle_bin_integrate", "oracle_smear_apply",
+                 "oracle_chi2", "oracle_chi2_dnu_complex_step"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -246,4 +251,69 @@ def chi2_complex_step(problem, model, theta, h=None):
     out = np.empty(5)
     _check(_load().oracle_chi2_complex_step(C.byref(d), _ptr(th), _ptr(hh), _ptr(out)),
            "chi2_complex_step")
+    return out
+
+
+def bin_integrate(x, ppb, w=None):
+    """mu[v, j] = sum_i w[j ppb + i] x[v, j ppb + i] for x[n_vec, n_bins ppb]
+    (or one vector); w None: weights 1."""
+    x = _f64(x)
+    one = x.ndim == 1
+    x2 = x.reshape(1, -1) if one else x
+    npts = x2.shape[1]
+    if npts % ppb:
+        raise ValueError("vector length is not a multiple of ppb")
+    nb = npts // ppb
+    wa = None if w is None else _f64(w)
+    if wa is not None and wa.size != npts:
+        raise ValueError("w has the wrong length")
+    mu = np.empty((x2.shape[0], nb))
+    _check(_load().oracle_bin_integrate(x2.shape[0], nb, ppb, _ptr(x2), _ptr(wa), _ptr(mu)),
+           "bin_integrate")
+    return mu[0] if one else mu
+
+
+def smear_apply(R, x, transpose=False):
+    """y = R x (transpose False) or R^T x, for x [n_vec, n] or one vector."""
+    R = _f64(R)
+    x = _f64(x)
+    one = x.ndim == 1
+    x2 = x.reshape(1, -1) if one else x
+    nr, nc = R.shape
+    n_in, n_out = (nr, nc) if transpose else (nc, nr)
+    if x2.shape[1] != n_in:
+        raise ValueError("x has the wrong length")
+    y = np.empty((x2.shape[0], n_out))
+    _check(_load().oracle_smear_apply(nr, nc, _ptr(R), int(bool(transpose)), x2.shape[0],
+                                      _ptr(x2), _ptr(y)), "smear_apply")
+    return y[0] if one else y
+
+
+def chi2_poisson(nu, d, grad=False):
+    """Baker-Cousins chi^2 of nu [n_vec, nb] (or one vector) against d [nb]
+    (shared) or d [n_vec, nb]; with grad, also d chi2/d nu."""
+    nu = _f64(nu)
+    d = _f64(d)
+    one = nu.ndim == 1
+    nu2 = nu.reshape(1, -1) if one else nu
+    nv, nb = nu2.shape
+    stride = 0 if d.ndim == 1 else nb
+    if d.shape[-1] != nb or (d.ndim == 2 and d.shape[0] != nv):
+        raise ValueError("d has the wrong shape")
+    c = np.empty(nv)
+    g = np.empty((nv, nb)) if grad else None
+    _check(_load().oracle_chi2(nb, nv, _ptr(nu2), _ptr(d), stride, _ptr(c), _ptr(g)), "chi2")
+    if one:
+        return (c[0], g[0]) if grad else c[0]
+    return (c, g) if grad else c
+
+
+def chi2_dnu_complex_step(nu, d, h=None):
+    """d chi2 / d nu_i = Im chi2(nu + i h_i e_i) / h_i for one vector."""
+    nu = _f64(nu).ravel()
+    d = _f64(d).ravel()
+    hh = _f64(h if h is not None else 1e-30 * np.abs(nu))
+    out = np.empty_like(nu)
+    _check(_load().oracle_chi2_dnu_complex_step(nu.size, _ptr(nu), _ptr(d), _ptr(hh), _ptr(out)),
+           "chi2_dnu_complex_step")
     return out

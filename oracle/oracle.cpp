@@ -599,4 +599,90 @@ int oracle_chi2_complex_step(const oracle_chain_desc* d, const double* params, c
   return OK;
 }
 
+// ---------------------------------------------------------------------------
+// The chain's steps as separate vector-in / vector-out transformations
+// (Sec. 2.1, Fig. 2: each transformation maps input vectors to an output
+// vector), over n_vec vectors stored one after another.
+// ---------------------------------------------------------------------------
+
+// Bin integration: mu[v][j] = sum_{i < ppb} w[j ppb + i] x[v][j ppb + i]
+// (w NULL: every weight 1), the terms added in ascending i.
+int oracle_bin_integrate(int64_t n_vec, int32_t nb, int32_t ppb, const double* x,
+                         const double* w, double* mu) {
+  if (n_vec < 0 || nb < 1 || ppb < 1 || (n_vec > 0 && (!x || !mu))) return E_INVAL;
+  const int64_t npts = (int64_t)nb * ppb;
+  for (int64_t v = 0; v < n_vec; ++v)
+    for (int j = 0; j < nb; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < ppb; ++i) {
+        const int64_t k = (int64_t)j * ppb + i;
+        acc += (w ? w[k] : 1.0) * x[v * npts + k];
+      }
+      mu[v * nb + j] = acc;
+    }
+  return OK;
+}
+
+// Smearing with a dense row-major R[n_rows][n_cols]:
+//   transpose = 0:  y[v][i] = sum_j R_ij x[v][j]   (x: n_cols, y: n_rows)
+//   transpose = 1:  y[v][j] = sum_i R_ij x[v][i]   (x: n_rows, y: n_cols)
+// the second being the adjoint step of the gradient (gmu = R^T gnu).
+int oracle_smear_apply(int32_t n_rows, int32_t n_cols, const double* R, int32_t transpose,
+                       int64_t n_vec, const double* x, double* y) {
+  if (n_rows < 1 || n_cols < 1 || !R || n_vec < 0 || (transpose != 0 && transpose != 1) ||
+      (n_vec > 0 && (!x || !y)))
+    return E_INVAL;
+  const int n_in = transpose ? n_rows : n_cols, n_out = transpose ? n_cols : n_rows;
+  for (int64_t v = 0; v < n_vec; ++v)
+    for (int o = 0; o < n_out; ++o) {
+      double acc = 0.0;
+      for (int c = 0; c < n_in; ++c) {
+        const double r = transpose ? R[(int64_t)c * n_cols + o] : R[(int64_t)o * n_cols + c];
+        acc += r * x[v * n_in + c];
+      }
+      y[v * n_out + o] = acc;
+    }
+  return OK;
+}
+
+// Baker-Cousins chi^2 of n_vec predictions nu[v][nb] against data
+// d + v d_stride (d_stride 0: one data vector for all), and optionally its
+// derivative d chi2 / d nu_i = 2 (1 - d_i / nu_i) into dchi2_dnu[v][nb].
+// Returns E_DOMAIN (outputs of that vector unset) if some nu_i <= 0.
+int oracle_chi2(int32_t nb, int64_t n_vec, const double* nu, const double* d, int64_t d_stride,
+                double* chi2, double* dchi2_dnu) {
+  if (nb < 1 || n_vec < 0 || d_stride < 0 || (n_vec > 0 && (!nu || !d || !chi2))) return E_INVAL;
+  int status = OK;
+  for (int64_t v = 0; v < n_vec; ++v) {
+    const double* nv = nu + v * nb;
+    const double* dv = d + v * d_stride;
+    const int rc = chi2_of<double>(nb, nv, dv, chi2 + v);
+    if (rc != OK) {
+      if (status == OK) status = rc;
+      continue;
+    }
+    if (dchi2_dnu)
+      for (int i = 0; i < nb; ++i) dchi2_dnu[v * nb + i] = 2.0 * (1.0 - dv[i] / nv[i]);
+  }
+  return status;
+}
+
+// Complex-step derivative of the chi^2 above with respect to each nu_i:
+// out[i] = Im chi2(nu + i h_i e_i) / h_i (pins the closed form 2 (1 - d/nu)
+// without using it).
+int oracle_chi2_dnu_complex_step(int32_t nb, const double* nu, const double* d, const double* h,
+                                 double* out) {
+  if (nb < 1 || !nu || !d || !h || !out) return E_INVAL;
+  std::vector<cplx> z(nb);
+  for (int i = 0; i < nb; ++i) {
+    for (int k = 0; k < nb; ++k) z[k] = cplx(nu[k], 0.0);
+    z[i] = cplx(nu[i], h[i]);
+    cplx c;
+    const int rc = chi2_of<cplx>(nb, z.data(), d, &c);
+    if (rc != OK) return rc;
+    out[i] = c.imag() / h[i];
+  }
+  return OK;
+}
+
 }  // extern "C"

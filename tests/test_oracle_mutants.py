@@ -69,6 +69,13 @@ MUTANTS = {
     "baseline weight ignored":
         ("acc += wr * pee_point<double>(E[i], L[r], theta[0], theta[1], theta[2], theta[3]);",
          "acc += pee_point<double>(E[i], L[r], theta[0], theta[1], theta[2], theta[3]);"),
+    "bin integration without its weights":
+        ("acc += (w ? w[k] : 1.0) * x[v * npts + k];", "acc += x[v * npts + k];"),
+    "smearing transform contracts against the reversed vector":
+        ("acc += r * x[v * n_in + c];", "acc += r * x[v * n_in + (n_in - 1 - c)];"),
+    "d chi2 / d nu with the wrong sign of the data term":
+        ("dchi2_dnu[v * nb + i] = 2.0 * (1.0 - dv[i] / nv[i]);",
+         "dchi2_dnu[v * nb + i] = 2.0 * (1.0 + dv[i] / nv[i]);"),
 }
 
 

@@ -450,6 +450,82 @@ def test_chi2_zero_data_and_pearson_limit():
     assert abs(c - pearson) <= 2e-3 * pearson
 
 
+# --------------------------------------------------------------------------
+# The chain's steps as separate transformations (bin integration, smearing
+# and its transpose, chi^2 with its derivative with respect to nu).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("order", [1, 3, 5, 8])
+def test_bin_integrate_exact_on_polynomials(order):
+    """With Gauss-Legendre points and weights as x = E^m and w, the bin sums
+    are the exact integrals (e_{j+1}^{m+1} - e_j^{m+1}) / (m + 1), m <= 2n - 1."""
+    edges = np.array([1.8, 2.0, 2.7, 3.1, 5.0, 8.5, 12.0])
+    n_sub = 2
+    E, w = oracle.quadrature(edges, order, n_sub)
+    ppb = order * n_sub
+    for m in range(2 * order):
+        mu = oracle.bin_integrate(E ** m, ppb, w)
+        exact = (edges[1:] ** (m + 1) - edges[:-1] ** (m + 1)) / (m + 1)
+        assert np.max(np.abs(mu - exact) / np.abs(exact)) <= 1e-13, m
+    # without weights: plain sums of each bin's ppb values, one row per vector
+    x = np.arange(3 * edges.size - 3, dtype=float).reshape(3, -1)
+    mu = oracle.bin_integrate(np.repeat(x, ppb, axis=1), ppb)
+    assert np.array_equal(mu, ppb * x)
+
+
+def test_smear_apply_against_matmul_and_adjoint_identity():
+    """R x and R^T x against numpy's products, and <g, R x> = <R^T g, x>, for
+    the 240-bin resolution matrix and a rectangular random matrix."""
+    rng = np.random.default_rng(7)
+    R = oracle.smearing(W.config0()["edges"], 0.03)
+    Rr = rng.uniform(-1, 1, (7, 11))
+    for M in (R, Rr):
+        nr, nc = M.shape
+        x = rng.uniform(0.5, 2.0, (3, nc))
+        g = rng.uniform(-1.0, 1.0, (3, nr))
+        y = oracle.smear_apply(M, x)
+        yt = oracle.smear_apply(M, g, transpose=True)
+        assert y.shape == (3, nr) and yt.shape == (3, nc)
+        assert np.max(np.abs(y - x @ M.T)) <= 1e-14 * np.abs(x @ np.abs(M).T).max()
+        assert np.max(np.abs(yt - g @ M)) <= 1e-14 * np.abs(np.abs(g) @ np.abs(M)).max()
+        lhs = np.sum(g * y, axis=1)
+        rhs = np.sum(yt * x, axis=1)
+        assert np.max(np.abs(lhs - rhs)) <= 1e-13 * np.sum(np.abs(g) @ np.abs(M) * x)
+        # one vector in, one vector out
+        assert np.array_equal(oracle.smear_apply(M, x[1]), y[1])
+
+
+def test_chi2_transform_against_scipy_and_its_derivative():
+    """chi^2 of a prediction vector against scipy's Poisson log-likelihood
+    ratio; d chi^2/d nu against the complex step and against central
+    differences of scipy's ratio; zero data gives 2 sum nu and slope 2."""
+    pr, nu = _cfg0_problem()
+    d = pr["data"]
+    nu1 = nu * (1.0 + 0.02 * np.cos(np.arange(nu.size)))
+
+    def ratio(v):
+        return 2.0 * np.sum(stats.poisson.logpmf(d, np.maximum(d, 1e-300)) * (d > 0)
+                            - stats.poisson.logpmf(d, v))
+
+    c, g = oracle.chi2_poisson(nu1, d, grad=True)
+    assert abs(c - ratio(nu1)) <= 1e-10 * c
+    gcs = oracle.chi2_dnu_complex_step(nu1, d)
+    assert np.max(np.abs(g - gcs)) <= 1e-12 * np.max(np.abs(gcs))
+    for i in (0, 17, 120, 239):
+        h = 1e-4 * nu1[i]
+        e = np.zeros(nu1.size)
+        e[i] = h
+        fd = (ratio(nu1 + e) - ratio(nu1 - e)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3), i
+    c0, g0 = oracle.chi2_poisson(nu1, np.zeros_like(d), grad=True)
+    assert abs(c0 - 2.0 * nu1.sum()) <= 1e-13 * c0 and np.all(g0 == 2.0)
+    # rows of a batch, against one data vector or one data vector per row
+    V = np.stack([nu, nu1, 1.1 * nu])
+    cb = oracle.chi2_poisson(V, d)
+    assert cb[0] == oracle.chi2_poisson(nu, d) and cb[1] == c
+    cd = oracle.chi2_poisson(V, np.stack([d, d, V[2]]))
+    assert cd[2] == 0.0 and cd[1] == c
+
+
 def test_chain_zero_resolution_means_no_smearing():
     pr, _ = _cfg0_problem()
     out = oracle.chain(pr, W.model(res_a=0.0), TH, grad=False, mu=True, nu=True)

@@ -15,7 +15,9 @@
  *   - data lives on the outputs, inputs are views (Sec. 2.1, Sec. 4.2);
  *   - all memory is allocated at the configuration stage (Sec. 4.2): this
  *     library never allocates device memory -- the caller hands it every
- *     buffer, including a workspace sized by the *_workspace_size calls;
+ *     buffer, including a workspace sized by the *_workspace_size calls (the
+ *     one exception is the fixed static staging array of
+ *     gna_pee_host_noalloc, loaded with the library's device code);
  *   - the status of the GPU computation is available on the host afterwards
  *     (Sec. 4.2): every call returns a status code, and device-side domain
  *     errors are latched in the plan and read with gna_plan_status.
@@ -142,6 +144,39 @@ int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const double* L_k
                  const double* wL_host, const double* theta_host, void* P_host, int32_t prec,
                  void* workspace_dev, size_t workspace_bytes, int64_t chunk, int32_t n_streams,
                  void* stream);
+
+/*
+ * For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc, code that must not grow its footprint): the
+ * pipeline of gna_pee_host with its staging buffers in a static device array
+ * of the library (GNA_NOALLOC_SCRATCH_BYTES per device, held from the first
+ * call on that device until the process ends) instead of a caller workspace.
+ * Same arguments, results (bit for bit) and synchronous behaviour as
+ * gna_pee_host without workspace_dev / workspace_bytes.
+ *   chunk, n_streams  n_streams slots of `chunk` energies and `chunk` results
+ *                     (each rounded up to 256 bytes) must fit the array:
+ *                     n_streams * (chunk*8 + chunk*(8 or 4)) <= 32 MiB, e.g.
+ *                     4 streams of 2^19 FP64 energies; larger requests fail
+ *                     with GNA_E_INVAL before any HIP call.
+ * Set-up: the first call on a device (or gna_device_init) resolves that
+ * device's address of the array and creates the pipeline streams shared with
+ * gna_pee_host; later calls allocate and create nothing.  The array keeps the
+ * last call's staging contents (nothing in it needs to start at zero).  Calls
+ * of both pipelined entry points are serialized inside the library, so two
+ * threads never use the array at once; in one process only one pipelined call
+ * runs at a time.  Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+#define GNA_NOALLOC_SCRATCH_BYTES (32u << 20)
+int gna_pee_host_noalloc(const double* E_host, int64_t n, int32_t n_L, const double* L_km_host,
+                         const double* wL_host, const double* theta_host, void* P_host,
+                         int32_t prec, int64_t chunk, int32_t n_streams, void* stream);
+/*
+ * Set-up of the library's per-device resources on the current device: the
+ * pipeline streams and event of gna_pee_host / gna_pee_host_noalloc and the
+ * device address of the no-allocation staging array.  Idempotent; the
+ * entry points above call it themselves.  Errors: GNA_E_HIP.
+ */
+int gna_device_init(void);
 
 /*
  * Streaming copy dst_dev[i] = src_dev[i], i < n: 16-byte non-temporal loads

@@ -73,6 +73,9 @@ SIGNATURES = {
                                               C.POINTER(C.c_size_t)]),
     "gna_pee_host": (C.c_int, [_vp, C.c_int64, C.c_int32, _dp, _dp, _dp, _vp, C.c_int32, _vp,
                                C.c_size_t, C.c_int64, C.c_int32, _vp]),
+    "gna_pee_host_noalloc": (C.c_int, [_vp, C.c_int64, C.c_int32, _dp, _dp, _dp, _vp, C.c_int32,
+                                       C.c_int64, C.c_int32, _vp]),
+    "gna_device_init": (C.c_int, []),
     "gna_prob": (C.c_int, [_vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _dp, _dp, _dp, _dp,
                            C.c_int32, _vp, C.c_int32, _vp]),
     "gna_chain_workspace_size": (C.c_int, [C.POINTER(Model), C.POINTER(Problem), C.c_int32,

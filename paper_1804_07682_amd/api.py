@@ -221,6 +221,37 @@ def gna_pee_host(E: torch.Tensor, L, theta, wL=None, prec="fp64", out: torch.Ten
     return out
 
 
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def gna_pee_host_noalloc(E: torch.Tensor, L, theta, wL=None, prec="fp64",
+                         out: torch.Tensor | None = None, chunk: int = 1 << 19,
+                         n_streams: int = 4, device="cuda"):
+    """gna_pee_host with the library's static staging array instead of a
+    workspace (``n_streams`` slots of ``chunk`` energies must fit 32 MiB).
+
+    E: CPU float64 [n]; returns a CPU tensor (float64 or float32).  Synchronous.
+    """
+    if not isinstance(E, torch.Tensor) or E.is_cuda or E.dtype != torch.float64 \
+            or not E.is_contiguous():
+        raise TypeError("E must be a contiguous CPU float64 tensor")
+    pr = _prec(prec)
+    L, wLa = _baselines(L, wL)
+    th = _theta4(theta)
+    odt = torch.float64 if pr == GNA_FP64 else torch.float32
+    n = E.numel()
+    if out is None:
+        out = torch.empty(n, dtype=odt, pin_memory=E.is_pinned())
+    elif out.is_cuda or out.dtype != odt or out.numel() != n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous CPU tensor of E's size and the output dtype")
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        check(load().gna_pee_host_noalloc(_ptr(E), n, L.size, _dptr(L), _dptr(wLa), _dptr(th),
+                                          _ptr(out), pr, int(chunk), int(n_streams),
+                                          _stream(dev)), "gna_pee_host_noalloc")
+    return out
+
+
 def gna_stream_copy(src: torch.Tensor, dst: torch.Tensor):
     """dst <- src with the elementwise kernel's access pattern (bandwidth reference)."""
     _need_cuda(src, "src")

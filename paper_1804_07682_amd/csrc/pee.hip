@@ -209,11 +209,21 @@ struct PipeDev {
   bool ready = false;
   hipStream_t st[GNA_PIPE_MAX_STREAMS];
   hipEvent_t start;
+  unsigned char* scratch = nullptr;  // this device's copy of `scratch` below
 };
 PipeDev g_pipe[kMaxDevices];
 std::mutex g_pipe_mu;   // guards g_pipe
 std::mutex g_pipe_run;  // one pipelined call at a time (they share streams and the event)
 
+// Staging buffers of gna_pee_host_noalloc: a file-scope device array, so that
+// entry point needs no workspace.  Every device that loads the library holds
+// its own copy until the process ends; host code reaches a device's copy only
+// through the address hipGetSymbolAddress returns with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)GNA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+// Library resources of the current device: the pipeline streams and event,
+// and the device address of `scratch`.  Idempotent.
 int pipe_resources(PipeDev*& out) {
   int dev = 0;
   int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
@@ -222,6 +232,12 @@ int pipe_resources(PipeDev*& out) {
   std::lock_guard<std::mutex> lock(g_pipe_mu);
   PipeDev& d = g_pipe[dev];
   if (!d.ready) {
+    void* addr = nullptr;
+    if ((rc = check_hip(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)),
+                        "hipGetSymbolAddress (no-allocation scratch)")))
+      return rc;
+    if (!addr || ((uintptr_t)addr & 255) != 0)
+      return fail(GNA_E_HIP, "no-allocation scratch at %p is not 256-byte aligned", addr);
     for (int k = 0; k < GNA_PIPE_MAX_STREAMS; ++k)
       if ((rc = check_hip(hipStreamCreateWithFlags(&d.st[k], hipStreamNonBlocking),
                           "hipStreamCreateWithFlags")))
@@ -229,6 +245,7 @@ int pipe_resources(PipeDev*& out) {
     if ((rc = check_hip(hipEventCreateWithFlags(&d.start, hipEventDisableTiming),
                         "hipEventCreateWithFlags")))
       return rc;
+    d.scratch = (unsigned char*)addr;
     d.ready = true;
   }
   out = &d;
@@ -238,6 +255,63 @@ int pipe_resources(PipeDev*& out) {
 size_t pipe_slot_bytes(int64_t chunk, int32_t prec) {
   const size_t osz = prec == GNA_FP64 ? 8 : 4;
   return align_up((size_t)chunk * 8, 256) + align_up((size_t)chunk * osz, 256);
+}
+
+// Host-side checks of the pipelined entry points; *need receives the staging
+// bytes (n_streams slots of chunk energies and chunk results).
+int check_pipe_args(const char* who, int64_t chunk, int32_t n_streams, int32_t prec,
+                    size_t* need) {
+  if (chunk < 2 || (chunk & 1))
+    return fail(GNA_E_INVAL, "%s: chunk = %lld must be even and >= 2", who, (long long)chunk);
+  if (n_streams < 1 || n_streams > GNA_PIPE_MAX_STREAMS)
+    return fail(GNA_E_INVAL, "%s: n_streams = %d outside 1..%d", who, n_streams,
+                GNA_PIPE_MAX_STREAMS);
+  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "%s: bad prec %d", who, prec);
+  *need = (size_t)n_streams * pipe_slot_bytes(chunk, prec);
+  return GNA_OK;
+}
+
+// The pipeline itself, on staging memory ws (device, 256-byte aligned, at
+// least n_streams slots).  ws == nullptr: this device's `scratch`.
+int pee_host_run(const double* E_host, int64_t n, int32_t n_L, const double* L_km_host,
+                 const double* wL_host, const double* theta_host, void* P_host, int32_t prec,
+                 unsigned char* ws, int64_t chunk, int32_t n_streams, void* stream) {
+  std::lock_guard<std::mutex> running(g_pipe_run);
+  PipeDev* pd = nullptr;
+  int rc = pipe_resources(pd);
+  if (rc) return rc;
+  if (!ws) ws = pd->scratch;
+  // Start after the work already queued on the caller's stream.
+  if ((rc = check_hip(hipEventRecord(pd->start, (hipStream_t)stream), "hipEventRecord")))
+    return rc;
+  for (int k = 0; k < n_streams; ++k)
+    if ((rc = check_hip(hipStreamWaitEvent(pd->st[k], pd->start, 0), "hipStreamWaitEvent")))
+      return rc;
+  const size_t osz = prec == GNA_FP64 ? 8 : 4;
+  const size_t slot = pipe_slot_bytes(chunk, prec);
+  // Chunk i on stream i % n_streams: a slot's buffers are reused only after
+  // the same (in-order) stream has copied its previous chunk back.
+  for (int64_t i = 0, off = 0; off < n; ++i, off += chunk) {
+    const int k = (int)(i % n_streams);
+    const int64_t m = std::min(chunk, n - off);
+    double* E_dev = (double*)(ws + k * slot);
+    void* P_dev = ws + k * slot + align_up((size_t)chunk * 8, 256);
+    hipStream_t s = pd->st[k];
+    if ((rc = check_hip(hipMemcpyAsync(E_dev, E_host + off, (size_t)m * 8, hipMemcpyHostToDevice, s),
+                        "hipMemcpyAsync (energies)")))
+      break;
+    if ((rc = launch_pee(E_dev, m, n_L, L_km_host, wL_host, theta_host, P_dev, prec, s))) break;
+    if ((rc = check_hip(hipMemcpyAsync((unsigned char*)P_host + (size_t)off * osz, P_dev,
+                                       (size_t)m * osz, hipMemcpyDeviceToHost, s),
+                        "hipMemcpyAsync (probabilities)")))
+      break;
+  }
+  // Drain every stream (also after an error, so no copy is left in flight).
+  for (int k = 0; k < n_streams; ++k) {
+    const int r2 = check_hip(hipStreamSynchronize(pd->st[k]), "hipStreamSynchronize");
+    if (!rc) rc = r2;
+  }
+  return rc;
 }
 
 }  // namespace
@@ -265,12 +339,7 @@ extern "C" int gna_pee_host_workspace_size(int64_t chunk, int32_t n_streams, int
   using namespace gna;
   clear_error();
   if (!bytes) return fail(GNA_E_INVAL, "gna_pee_host_workspace_size: NULL bytes");
-  if (chunk < 2 || (chunk & 1)) return fail(GNA_E_INVAL, "chunk = %lld must be even and >= 2", (long long)chunk);
-  if (n_streams < 1 || n_streams > GNA_PIPE_MAX_STREAMS)
-    return fail(GNA_E_INVAL, "n_streams = %d outside 1..%d", n_streams, GNA_PIPE_MAX_STREAMS);
-  if (prec != GNA_FP64 && prec != GNA_MIXED) return fail(GNA_E_INVAL, "bad prec %d", prec);
-  *bytes = (size_t)n_streams * pipe_slot_bytes(chunk, prec);
-  return GNA_OK;
+  return check_pipe_args("gna_pee_host_workspace_size", chunk, n_streams, prec, bytes);
 }
 
 extern "C" int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const double* L_km_host,
@@ -282,7 +351,7 @@ extern "C" int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const 
   int rc = check_pee_args("gna_pee_host", n, n_L, L_km_host, theta_host, prec);
   if (rc) return rc;
   size_t need = 0;
-  if ((rc = gna_pee_host_workspace_size(chunk, n_streams, prec, &need))) return rc;
+  if ((rc = check_pipe_args("gna_pee_host", chunk, n_streams, prec, &need))) return rc;
   if (n == 0) return GNA_OK;
   if (!E_host || !P_host) return fail(GNA_E_INVAL, "gna_pee_host: NULL host pointer");
   if (!workspace_dev || ((uintptr_t)workspace_dev & 255) != 0)
@@ -290,41 +359,36 @@ extern "C" int gna_pee_host(const double* E_host, int64_t n, int32_t n_L, const 
   if (workspace_bytes < need)
     return fail(GNA_E_WORKSPACE, "gna_pee_host: workspace %zu bytes, needs %zu", workspace_bytes,
                 need);
-  std::lock_guard<std::mutex> running(g_pipe_run);
+  return pee_host_run(E_host, n, n_L, L_km_host, wL_host, theta_host, P_host, prec,
+                      (unsigned char*)workspace_dev, chunk, n_streams, stream);
+}
+
+extern "C" int gna_pee_host_noalloc(const double* E_host, int64_t n, int32_t n_L,
+                                    const double* L_km_host, const double* wL_host,
+                                    const double* theta_host, void* P_host, int32_t prec,
+                                    int64_t chunk, int32_t n_streams, void* stream) {
+  using namespace gna;
+  clear_error();
+  int rc = check_pee_args("gna_pee_host_noalloc", n, n_L, L_km_host, theta_host, prec);
+  if (rc) return rc;
+  size_t need = 0;
+  if ((rc = check_pipe_args("gna_pee_host_noalloc", chunk, n_streams, prec, &need))) return rc;
+  if (need > kNoallocScratchBytes)
+    return fail(GNA_E_INVAL,
+                "gna_pee_host_noalloc: %d streams of %lld-element chunks need %zu staging bytes, "
+                "the static scratch holds %zu",
+                n_streams, (long long)chunk, need, kNoallocScratchBytes);
+  if (n == 0) return GNA_OK;
+  if (!E_host || !P_host) return fail(GNA_E_INVAL, "gna_pee_host_noalloc: NULL host pointer");
+  return pee_host_run(E_host, n, n_L, L_km_host, wL_host, theta_host, P_host, prec, nullptr,
+                      chunk, n_streams, stream);
+}
+
+extern "C" int gna_device_init(void) {
+  using namespace gna;
+  clear_error();
   PipeDev* pd = nullptr;
-  if ((rc = pipe_resources(pd))) return rc;
-  // Start after the work already queued on the caller's stream.
-  if ((rc = check_hip(hipEventRecord(pd->start, (hipStream_t)stream), "hipEventRecord")))
-    return rc;
-  for (int k = 0; k < n_streams; ++k)
-    if ((rc = check_hip(hipStreamWaitEvent(pd->st[k], pd->start, 0), "hipStreamWaitEvent")))
-      return rc;
-  const size_t osz = prec == GNA_FP64 ? 8 : 4;
-  const size_t slot = pipe_slot_bytes(chunk, prec);
-  unsigned char* ws = (unsigned char*)workspace_dev;
-  // Chunk i on stream i % n_streams: a slot's buffers are reused only after
-  // the same (in-order) stream has copied its previous chunk back.
-  for (int64_t i = 0, off = 0; off < n; ++i, off += chunk) {
-    const int k = (int)(i % n_streams);
-    const int64_t m = std::min(chunk, n - off);
-    double* E_dev = (double*)(ws + k * slot);
-    void* P_dev = ws + k * slot + align_up((size_t)chunk * 8, 256);
-    hipStream_t s = pd->st[k];
-    if ((rc = check_hip(hipMemcpyAsync(E_dev, E_host + off, (size_t)m * 8, hipMemcpyHostToDevice, s),
-                        "hipMemcpyAsync (energies)")))
-      break;
-    if ((rc = launch_pee(E_dev, m, n_L, L_km_host, wL_host, theta_host, P_dev, prec, s))) break;
-    if ((rc = check_hip(hipMemcpyAsync((unsigned char*)P_host + (size_t)off * osz, P_dev,
-                                       (size_t)m * osz, hipMemcpyDeviceToHost, s),
-                        "hipMemcpyAsync (probabilities)")))
-      break;
-  }
-  // Drain every stream (also after an error, so no copy is left in flight).
-  for (int k = 0; k < n_streams; ++k) {
-    const int r2 = check_hip(hipStreamSynchronize(pd->st[k]), "hipStreamSynchronize");
-    if (!rc) rc = r2;
-  }
-  return rc;
+  return pipe_resources(pd);
 }
 
 // ---------------------------------------------------------------------------

@@ -163,6 +163,32 @@ def test_pee_host_sizing_and_validation(lib):
     assert call(th_=np.array([7.5e-5, 2.5e-3, 1.3, 0.02])) == -1  # s12 outside [0, 1]
 
 
+def test_pee_host_noalloc_validation(lib):
+    """The no-allocation pipeline refuses staging beyond its static array, and
+    bad arguments, on the host before any HIP call."""
+    L = np.array([52.5])
+    th = np.array([7.5e-5, 2.5e-3, 0.3, 0.02])
+    dp = C.POINTER(C.c_double)
+    E = np.ones(8)
+    P = np.zeros(8)
+
+    def call(n=8, chunk=4096, ns=2, prec=0, Eh=E):
+        return lib.gna_pee_host_noalloc(Eh.ctypes.data if Eh is not None else None, n, 1,
+                                        L.ctypes.data_as(dp), None, th.ctypes.data_as(dp),
+                                        P.ctypes.data, prec, chunk, ns, None)
+
+    assert call(n=0) == 0
+    assert call(chunk=1 << 20, ns=4) == -1             # 64 MiB of staging > 32 MiB
+    assert b"static scratch" in lib.gna_last_error_message()
+    assert call(chunk=1 << 19, ns=4, n=0) == 0         # exactly 32 MiB fits (n = 0: no HIP call)
+    assert call(chunk=1 << 20, ns=2, n=0) == 0         # likewise
+    assert call(chunk=(1 << 19) + 2, ns=4) == -1       # 32 MiB + 2 KiB of slot padding
+    assert call(chunk=3 << 19, ns=2, prec=1) == -1     # mixed: 2 x (12 + 6) MiB
+    assert call(chunk=3) == -1                         # odd chunk
+    assert call(ns=5) == -1
+    assert call(Eh=None) == -1
+
+
 def test_binding_rejects_short_host_arrays(lib):
     """The C side reads n_L weights and n_bins data values: the binding refuses
     vectors of any other length before the call (no GPU needed)."""

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GNA_ABI_VERSION 4
+#define GNA_ABI_VERSION 5
 
 /* ---- status codes -------------------------------------------------------- */
 #define GNA_OK 0
@@ -362,10 +362,65 @@ int gna_plan_destroy(gna_plan* plan);
 
 /* ---- unfused transformations (vector in / vector out) -------------------- */
 /*
- * Gauss-Legendre rule of order 1..64 on [-1, 1] (nodes ascending, weights),
- * computed on the device into t_dev[order], w_dev[order].  Synchronous.
+ * The chain's steps as separate transformations (Sec. 2.1, Fig. 2: a
+ * transformation maps read-only input vectors to an output vector it owns;
+ * Sec. 4.2, Fig. 6: an intermediate result is read at the cost of one more
+ * output).  FP64, over a batch of n_vec vectors stored one after another
+ * (row-major [n_vec][length]); every sum is taken in a fixed order, so the
+ * results do not depend on scheduling.  Device pointers 8-byte aligned;
+ * n_vec = 0 is a no-op.  The fused chain entry points compute the same steps
+ * in one launch.
  */
-int gna_gl_nodes(int32_t order, double* t_dev, double* w_dev, void* stream);
+
+/*
+ * Gauss-Legendre rule of order 1..64 on [-1, 1] (nodes ascending; weights),
+ * computed on the device and returned in host memory: t_host[order],
+ * w_host[order].  Synchronous (the null stream).  Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_gl_nodes(int32_t order, double* t_host, double* w_host);
+/* The same rule into device memory t_dev[order], w_dev[order] on `stream`;
+ * synchronizes `stream`. */
+int gna_gl_nodes_dev(int32_t order, double* t_dev, double* w_dev, void* stream);
+
+/*
+ * Bin integration (the Gauss-Legendre sum of each bin):
+ *   mu_dev[v][j] = sum_{i < ppb} w_dev[j*ppb + i] * x_dev[v][j*ppb + i]
+ * for j < n_bins, v < n_vec; x_dev holds each vector's n_bins*ppb point
+ * values bin after bin (the quadrature-point order of the chain), w_dev the
+ * n_bins*ppb quadrature weights shared by all vectors, or NULL for weight 1
+ * (values already weighted, as f_k P_k is).  Asynchronous on `stream`.
+ * Errors: GNA_E_INVAL (sizes < 1, NULL, misaligned), GNA_E_HIP.
+ */
+int gna_bin_integrate(const double* x_dev, const double* w_dev, int64_t n_vec, int32_t n_bins,
+                      int32_t ppb, double* mu_dev, void* stream);
+
+/*
+ * Smearing with a dense row-major matrix R_dev[n_rows][n_cols] (row =
+ * reconstructed bin, column = true bin, as gna_plan_tables writes it):
+ *   transpose = 0:  y_dev[v][i] = sum_j R_ij x_dev[v][j]   (x: n_cols, y: n_rows)
+ *   transpose = 1:  y_dev[v][j] = sum_i R_ij x_dev[v][i]   (x: n_rows, y: n_cols)
+ * transpose = 1 is the adjoint step of the gradient, d chi^2/d mu = R^T
+ * d chi^2/d nu.  x_dev and y_dev must not overlap.  Asynchronous on `stream`.
+ * Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_smear(const double* R_dev, int32_t n_rows, int32_t n_cols, int32_t transpose,
+              const double* x_dev, int64_t n_vec, double* y_dev, void* stream);
+
+/*
+ * Baker-Cousins Poisson chi^2 of n_vec predictions nu_dev[v][n_bins]:
+ *   chi2_dev[v] = 2 sum_i [nu_i - d_i + d_i ln(d_i / nu_i)]  (d ln(d/nu) = 0 at d = 0)
+ * and, if dchi2_dnu_dev is not NULL, its derivative
+ *   dchi2_dnu_dev[v][i] = 2 (1 - d_i / nu_i),
+ * the seed of the adjoint pass.  data_dev holds the observed counts (>= 0):
+ * one vector shared by all predictions (data_stride = 0) or one per
+ * prediction (data_stride = n_bins).  A prediction with some nu_i <= 0 (or
+ * NaN) gives chi2 = NaN for that vector and NaN in the offending derivative
+ * entries (no status word: these calls have no plan).  Asynchronous on
+ * `stream`.  Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_chi2(const double* nu_dev, const double* data_dev, int64_t data_stride, int32_t n_bins,
+             int64_t n_vec, double* chi2_dev, double* dchi2_dnu_dev, void* stream);
+
 /*
  * Configuration-stage tables of problem `index` of a plan (Fig. 6-style
  * intermediate read): quadrature energies E_dev[n_bins*ppb], flux factors

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libgna_hip.so")
 
-ABI_VERSION = 4  # the layout of the structs below
+ABI_VERSION = 5  # the layout of the structs below
 GNA_OK = 0
 GNA_E_INVAL = -1
 GNA_E_DOMAIN = -2
@@ -97,7 +97,11 @@ SIGNATURES = {
     "gna_plan_autotune": (C.c_int, [_PlanP, _vp, C.c_int32, _vp, _vp, C.c_int32, C.c_char_p,
                                     _vp, C.POINTER(C.c_int32)]),
     "gna_plan_destroy": (C.c_int, [_PlanP]),
-    "gna_gl_nodes": (C.c_int, [C.c_int32, _vp, _vp, _vp]),
+    "gna_gl_nodes": (C.c_int, [C.c_int32, _dp, _dp]),
+    "gna_gl_nodes_dev": (C.c_int, [C.c_int32, _vp, _vp, _vp]),
+    "gna_bin_integrate": (C.c_int, [_vp, _vp, C.c_int64, C.c_int32, C.c_int32, _vp, _vp]),
+    "gna_smear": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, C.c_int64, _vp, _vp]),
+    "gna_chi2": (C.c_int, [_vp, _vp, C.c_int64, C.c_int32, C.c_int64, _vp, _vp, _vp]),
     "gna_plan_tables": (C.c_int, [_PlanP, C.c_int32, _vp, _vp, _vp, _vp]),
     "gna_graph_create": (C.c_int, [C.POINTER(_GraphP)]),
     "gna_graph_destroy": (C.c_int, [_GraphP]),

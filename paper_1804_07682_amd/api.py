@@ -263,11 +263,81 @@ def gna_stream_copy(src: torch.Tensor, dst: torch.Tensor):
     return dst
 
 
-def gna_gl_nodes(order: int, device="cuda"):
+def gna_gl_nodes(order: int):
+    """Gauss-Legendre rule of order 1..64 on [-1, 1], computed on the device
+    and returned as host float64 arrays (nodes ascending, weights)."""
+    t = np.empty(int(order), dtype=np.float64)
+    w = np.empty(int(order), dtype=np.float64)
+    check(load().gna_gl_nodes(int(order), _dptr(t), _dptr(w)), "gna_gl_nodes")
+    return t, w
+
+
+def gna_gl_nodes_dev(order: int, device="cuda"):
+    """The Gauss-Legendre rule into device tensors (nodes, weights)."""
     t = torch.empty(order, dtype=torch.float64, device=device)
     w = torch.empty(order, dtype=torch.float64, device=device)
-    check(load().gna_gl_nodes(order, _ptr(t), _ptr(w), _stream(t.device)), "gna_gl_nodes")
+    check(load().gna_gl_nodes_dev(order, _ptr(t), _ptr(w), _stream(t.device)), "gna_gl_nodes_dev")
     return t, w
+
+
+def _rows(x: torch.Tensor, name: str, length: int):
+    """A CUDA float64 vector [length] or batch [n_vec, length], as (2-D view, 1-D?)."""
+    _need_cuda(x, name)
+    one = x.dim() == 1
+    x2 = x.reshape(1, -1) if one else x
+    if x2.dim() != 2 or x2.shape[1] != length:
+        raise ValueError(f"{name} must be [{length}] or [n_vec, {length}], got {tuple(x.shape)}")
+    return x2, one
+
+
+def gna_bin_integrate(x: torch.Tensor, n_bins: int, ppb: int, w: torch.Tensor | None = None):
+    """mu[v, j] = sum_i w[j ppb + i] x[v, j ppb + i] (w None: weights 1)."""
+    nb, ppb = int(n_bins), int(ppb)
+    x2, one = _rows(x, "x", nb * ppb)
+    if w is not None:
+        _need_cuda(w, "w")
+        if w.numel() != nb * ppb:
+            raise ValueError("w must hold n_bins * ppb weights")
+    mu = torch.empty((x2.shape[0], nb), dtype=torch.float64, device=x.device)
+    check(load().gna_bin_integrate(_ptr(x2), _ptr(w), x2.shape[0], nb, ppb, _ptr(mu),
+                                   _stream(x.device)), "gna_bin_integrate")
+    return mu[0] if one else mu
+
+
+def gna_smear(R: torch.Tensor, x: torch.Tensor, transpose: bool = False):
+    """y = R x (or R^T x) for a dense row-major R and x [n] or [n_vec, n]."""
+    _need_cuda(R, "R")
+    if R.dim() != 2:
+        raise ValueError("R must be a matrix")
+    nr, nc = R.shape
+    n_in, n_out = (nr, nc) if transpose else (nc, nr)
+    x2, one = _rows(x, "x", n_in)
+    y = torch.empty((x2.shape[0], n_out), dtype=torch.float64, device=x.device)
+    check(load().gna_smear(_ptr(R), nr, nc, int(bool(transpose)), _ptr(x2), x2.shape[0], _ptr(y),
+                           _stream(x.device)), "gna_smear")
+    return y[0] if one else y
+
+
+def gna_chi2(nu: torch.Tensor, data: torch.Tensor, grad: bool = False):
+    """Baker-Cousins chi^2 of nu [nb] or [n_vec, nb] against data [nb] (shared)
+    or [n_vec, nb]; with grad, also d chi^2 / d nu (same shape as nu)."""
+    _need_cuda(data, "data")
+    nb = data.shape[-1]
+    nu2, one = _rows(nu, "nu", nb)
+    n_vec = nu2.shape[0]
+    if data.dim() == 1:
+        stride = 0
+    elif tuple(data.shape) == (n_vec, nb):
+        stride = nb
+    else:
+        raise ValueError("data must be [nb] or [n_vec, nb]")
+    c = torch.empty(n_vec, dtype=torch.float64, device=nu.device)
+    g = torch.empty((n_vec, nb), dtype=torch.float64, device=nu.device) if grad else None
+    check(load().gna_chi2(_ptr(nu2), _ptr(data), stride, nb, n_vec, _ptr(c), _ptr(g),
+                          _stream(nu.device)), "gna_chi2")
+    if one:
+        return (c[0], g[0]) if grad else c[0]
+    return (c, g) if grad else c
 
 
 class _PlanBase:

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "gna_internal.h"
@@ -76,6 +77,11 @@ __global__ void gl_table_kernel(double* __restrict__ t, double* __restrict__ w) 
 __global__ void gl_one_kernel(int n, double* __restrict__ t, double* __restrict__ w) {
   gl_rule(n, t, w);
 }
+
+// Staging of the host-output rule (gna_gl_nodes): nodes, then weights.
+static __device__ double gl_stage[2 * kMaxOrder];
+
+__global__ void gl_stage_kernel(int n) { gl_rule(n, gl_stage, gl_stage + kMaxOrder); }
 
 // ---------------------------------------------------------------------------
 // Quadrature energies and flux factors, one lane per point (grid.y = problem).
@@ -880,7 +886,7 @@ extern "C" int gna_plan_destroy(gna_plan* plan) {
   return GNA_OK;
 }
 
-extern "C" int gna_gl_nodes(int32_t order, double* t_dev, double* w_dev, void* stream) {
+extern "C" int gna_gl_nodes_dev(int32_t order, double* t_dev, double* w_dev, void* stream) {
   clear_error();
   if (order < 1 || order > kMaxOrder)
     return fail(GNA_E_INVAL, "order = %d outside 1..%d", order, kMaxOrder);
@@ -890,6 +896,29 @@ extern "C" int gna_gl_nodes(int32_t order, double* t_dev, double* w_dev, void* s
   int rc = check_hip(hipGetLastError(), "gl_one_kernel");
   if (rc) return rc;
   return check_hip(hipStreamSynchronize(s), "hipStreamSynchronize (gl nodes)");
+}
+
+namespace {
+std::mutex g_gl_stage_mu;  // one host-output rule at a time (shared staging array)
+}
+
+extern "C" int gna_gl_nodes(int32_t order, double* t_host, double* w_host) {
+  clear_error();
+  if (order < 1 || order > kMaxOrder)
+    return fail(GNA_E_INVAL, "order = %d outside 1..%d", order, kMaxOrder);
+  if (!t_host || !w_host) return fail(GNA_E_INVAL, "NULL output");
+  std::lock_guard<std::mutex> lock(g_gl_stage_mu);
+  hipLaunchKernelGGL(gl_stage_kernel, dim3(1), dim3(32), 0, nullptr, (int)order);
+  int rc = check_hip(hipGetLastError(), "gl_stage_kernel");
+  if (rc) return rc;
+  // Copies on the null stream run after the kernel and return when done.
+  if ((rc = check_hip(hipMemcpyFromSymbol(t_host, HIP_SYMBOL(gl_stage), sizeof(double) * order, 0,
+                                          hipMemcpyDeviceToHost),
+                      "hipMemcpyFromSymbol (nodes)")))
+    return rc;
+  return check_hip(hipMemcpyFromSymbol(w_host, HIP_SYMBOL(gl_stage), sizeof(double) * order,
+                                       sizeof(double) * kMaxOrder, hipMemcpyDeviceToHost),
+                   "hipMemcpyFromSymbol (weights)");
 }
 
 extern "C" int gna_plan_tables(const gna_plan* plan, int32_t index, double* E_dev, double* f_dev,

@@ -33,7 +33,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("gna_pee", "gna_chain_create", "gna_chain_eval", "gna_fitset_eval",
-                 "gna_plan_status", "gna_plan_autotune", "gna_gl_nodes", "gna_plan_tables"):
+                 "gna_plan_status", "gna_plan_autotune", "gna_gl_nodes", "gna_plan_tables",
+                 "gna_bin_integrate", "gna_smear", "gna_chi2"):
         assert must in names
 
 
@@ -45,7 +46,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_strings(lib):
-    assert lib.gna_abi_version() == 4
+    assert lib.gna_abi_version() == 5
     for code in (0, -1, -2, -3, -4, -5, 17):
         assert lib.gna_strerror(code)
     assert lib.gna_strerror(-4).decode().startswith("workspace")
@@ -187,6 +188,32 @@ def test_pee_host_noalloc_validation(lib):
     assert call(chunk=3) == -1                         # odd chunk
     assert call(ns=5) == -1
     assert call(Eh=None) == -1
+
+
+def test_unfused_transforms_validate_on_the_host(lib):
+    """Sizes, flags and NULL outputs of the unfused transformations are refused
+    before any launch; n_vec = 0 is a no-op (no HIP call)."""
+    p = C.c_void_p(256)
+    assert lib.gna_bin_integrate(p, None, 0, 240, 5, p, None) == 0
+    assert lib.gna_bin_integrate(p, None, 1, 0, 5, p, None) == -1
+    assert lib.gna_bin_integrate(p, None, 1, 240, 0, p, None) == -1
+    assert lib.gna_bin_integrate(p, None, -1, 240, 5, p, None) == -1
+    assert lib.gna_bin_integrate(None, None, 1, 240, 5, p, None) == -1
+    assert lib.gna_bin_integrate(C.c_void_p(260), None, 1, 240, 5, p, None) == -1
+    assert lib.gna_smear(p, 240, 240, 0, p, 0, p, None) == 0
+    assert lib.gna_smear(p, 240, 240, 2, p, 1, p, None) == -1
+    assert lib.gna_smear(p, 0, 240, 0, p, 1, p, None) == -1
+    assert lib.gna_smear(p, 240, 240, 1, p, 1, None, None) == -1
+    assert lib.gna_chi2(p, p, 0, 240, 0, p, None, None) == 0
+    assert lib.gna_chi2(p, p, 7, 240, 1, p, None, None) == -1   # stride neither 0 nor n_bins
+    assert lib.gna_chi2(p, p, 0, 0, 1, p, None, None) == -1
+    assert lib.gna_chi2(p, None, 0, 240, 1, p, None, None) == -1
+    t = np.zeros(65)
+    w = np.zeros(65)
+    dp = C.POINTER(C.c_double)
+    assert lib.gna_gl_nodes(65, t.ctypes.data_as(dp), w.ctypes.data_as(dp)) == -1
+    assert lib.gna_gl_nodes(0, t.ctypes.data_as(dp), w.ctypes.data_as(dp)) == -1
+    assert lib.gna_gl_nodes(5, None, w.ctypes.data_as(dp)) == -1
 
 
 def test_binding_rejects_short_host_arrays(lib):

@@ -178,7 +178,9 @@ def test_tables_match_oracle(cfg2):
 def test_gl_nodes_match_oracle():
     import paper_1804_07682_amd as gna
     for n in (1, 2, 3, 5, 10, 17, 64):
-        t, w = (x.cpu().numpy() for x in gna.gna_gl_nodes(n))
+        t, w = gna.gna_gl_nodes(n)  # host output
+        td, wd = (x.cpu().numpy() for x in gna.gna_gl_nodes_dev(n))
+        assert np.array_equal(t, td) and np.array_equal(w, wd)
         to, wo = oracle.gauss_legendre(n)
         assert np.max(np.abs(t - to)) <= 2.3e-16
         assert np.max(np.abs(w - wo) / wo) <= 64 * 2.3e-16

@@ -4,30 +4,37 @@ A step is one evaluation of the whole chain -- P_ee, flux x cross section,
 Gauss-Legendre bin integration, smearing, Poisson chi^2 and its 5-component
 gradient -- for the batched scan: 4096 parameter points on a 64 x 64 grid in
 (dm2_31, sin^2 th13), 240 bins x 5 Gauss-Legendre nodes (1200 points), one
-52.5 km baseline, mixed precision.  `value` is chi^2+gradient evaluations per
-second (parameter points per second), inputs resident in HBM.  Tiles of 16
-points with common (dm2_21, dm2_31) -- every tile of this grid, whose fast
-axis is sin^2 th13 -- evaluate their phases once (the library's default).
+52.5 km baseline, in FP64.  `value` is chi^2+gradient evaluations per second
+(parameter points per second), inputs resident in HBM.  Tiles of 16 points
+with common (dm2_21, dm2_31) -- every tile of this grid, whose fast axis is
+sin^2 th13 -- evaluate their phases once (the library's default); the roofline
+states the fraction of the ALU peak both for that executed work and for the
+per-point count of a kernel that shares nothing.
 
 The same JSON line also carries, measured in this run:
-  * fp64: the same scan in plain FP64;
-  * per_point_phases: the same scan with phase sharing switched off (every
-    point evaluates its own phases), mixed and FP64;
+  * mixed: the same scan in mixed precision (FP64 phases, FP32 elsewhere);
+  * per_point_phases: the grid with phase sharing switched off, FP64 and mixed;
+  * random_batch: 4096 points that share nothing (every parameter drawn
+    around the reference point), FP64 and mixed;
+  * mixed_vs_fp64: per output (prediction, chi^2, gradient) for the grid
+    scan, the random batch, the 1200-point and the 8-baseline single-point
+    chains; the uneven batch's is under fitset, P_ee's under pee_sweep;
   * pee: elementwise P_ee over N = 1e8 energies (52.5 km) in FP64 and mixed,
     evaluations/s and HBM bandwidth against 8 TB/s;
   * pee_sweep: the same over N in {1e6, 1e7, 1e8} and L in {1, 52.5, 1300} km,
     with the mixed-vs-FP64 error per baseline;
   * chain_1pt / chain_8L / fitset: the single-point chain (1200 points), the
     single-point chain with 8 baselines and 100 800 points, and the uneven
-    batch of 1024 fits (evaluations/s, FP64 and mixed); the single-point
-    chains also replayed from a captured HIP graph;
-  * mixed_vs_fp64: max errors of the mixed scan against FP64 per output;
+    batch of 1024 fits (evaluations/s, FP64 and mixed; the fitset as the
+    autotuned shape and as one persistent launch); the single-point chains
+    also replayed from a captured HIP graph;
   * transfer_pipeline: P_ee over N = 1e8 energies in host memory, copies in
     and out serialized against the library's pipelined transfers;
   * graph: the transformation graph of the config-0 chain read back after a
     change of dm2_31 (full recompute) or of the normalisation only (lazy:
     two nodes), beside the fused chain;
-  * roofline of the dominant kernel, cpu_baseline of the oracle.
+  * roofline of the dominant kernel, cpu_baseline of the oracle (all host
+    threads and one thread, with the CPU model).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -181,7 +188,7 @@ TUNE = True
 STREAM_WARMUP = 120
 
 
-def scan_setup(gna, W, torch, prec, dev, share=True):
+def scan_setup(gna, W, torch, prec, dev, share=True, params=None):
     model = W.model()
     pr = W.config0()
     # Pseudo-data: Poisson counts drawn from this library's own FP64 prediction.
@@ -189,7 +196,8 @@ def scan_setup(gna, W, torch, prec, dev, share=True):
     nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
                   pred=True)["pred"].cpu().numpy()[0]
     pr["data"] = W.poisson_counts(nu, W.SEED)
-    P = torch.tensor(W.config3_params(), dtype=torch.float64, device=dev)
+    P = torch.tensor(W.config3_params() if params is None else params, dtype=torch.float64,
+                     device=dev)
     plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev,
                      opts=None if share else {"no_shared_phases": 1})
     if TUNE:
@@ -197,8 +205,8 @@ def scan_setup(gna, W, torch, prec, dev, share=True):
     return pr, model, plan, P
 
 
-def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup, share=True):
-    pr, model, plan, P = scan_setup(gna, W, torch, prec, dev, share)
+def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup, share=True, params=None):
+    pr, model, plan, P = scan_setup(gna, W, torch, prec, dev, share, params)
     out = {"chi2": torch.empty(P.shape[0], dtype=torch.float64, device=dev),
            "grad": torch.empty((P.shape[0], 5), dtype=torch.float64, device=dev)}
     fn = lambda: plan.eval(P, grad=True, out=out)
@@ -206,10 +214,14 @@ def bench_scan(gna, W, torch, timer, prec, dev, steps, warmup, share=True):
     kmean = timer.period
     plan.status()
     flops = scan_flops(P.cpu().numpy(), 1200, 240, share)
+    # The per-point count: every (quadrature point, parameter point) pays a
+    # full P_ee + tangents evaluation, shared phases or not.
+    pp_flops = P.shape[0] * 1200 * FLOPS_PER_PEE_GRAD_EVAL
     return {"plan": plan, "pr": pr, "P": P, "wall": wall, "kernel_s": kmean,
             "event_pair_s": kpair, "event_pair_med_s": kmed,
             "evals_per_s": P.shape[0] * steps / wall, "shape": plan.shape(),
-            "flops": flops, "tflops": flops / kmean / 1e12}
+            "flops": flops, "tflops": flops / kmean / 1e12,
+            "pp_flops": pp_flops, "pp_tflops": pp_flops / kmean / 1e12}
 
 
 def bench_pee(gna, W, torch, timer, dev, n, L, prec, steps):
@@ -316,7 +328,7 @@ def graph_rate(torch, fn, steps, per_graph=20):
             "evals_per_graph": per_graph}
 
 
-def bench_fitset(gna, W, torch, timer, dev, steps, prec):
+def bench_fitset(gna, W, torch, timer, dev, steps, prec, opts=None, tune=True):
     model = W.model()
     problems, params = W.config4()
     # Pseudo-data per fit from this library's FP64 prediction at THETA0.
@@ -329,14 +341,17 @@ def bench_fitset(gna, W, torch, timer, dev, steps, prec):
         nb = len(pb["edges"]) - 1
         pb["data"] = W.poisson_counts(nu[off:off + nb], W.config4_data_seed(f))
         off += nb
-    plan = gna.FitSet(problems, model, prec=prec, device=dev)
+    plan = gna.FitSet(problems, model, prec=prec, device=dev, opts=opts)
     P = torch.tensor(params, device=dev)
-    if TUNE:
+    if TUNE and tune:
         plan.autotune(P, reps=3)
     wall, _, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
     kmean = timer.period
+    shape = plan.shape()
+    # A split tail is the point pass plus two tail launches; otherwise one launch.
     return {"fits_per_s": len(problems) * steps / wall, "kernel_ms": kmean * 1e3,
-            "shape": plan.shape()}
+            "launches": 3 if shape["split_tail"] else 1, "shape": shape,
+            "problems": problems, "plan": plan, "P": P}
 
 
 def table1_gpu(gna, W, torch, timer, dev):
@@ -468,21 +483,67 @@ def table1_cpu(W, threads):
     return res
 
 
+GRAD_ERR_DEF = ("max over points and components of |theta_c (g_mixed - g_fp64)| / "
+                "max(|theta_c g_fp64|, chi2_fp64, 1)")
+
+
+def output_errors(a, b, th):
+    """Largest error of mixed-precision outputs `a` against FP64 outputs `b` per
+    output: the prediction nu (relative), chi^2 (relative and absolute) and the
+    gradient (scaled: it is ~0 near a minimum, see GRAD_ERR_DEF)."""
+    res = {"pred_max_rel": float(np.max(np.abs(a["pred"] - b["pred"]) / np.abs(b["pred"]))),
+           "chi2_max_rel": float(np.max(np.abs(a["chi2"] - b["chi2"]) / np.abs(b["chi2"]))),
+           "chi2_max_abs": float(np.max(np.abs(a["chi2"] - b["chi2"])))}
+    th = np.atleast_2d(th)
+    scale = np.maximum(np.maximum(np.abs(th * b["grad"]), b["chi2"][:, None]), 1.0)
+    res["grad_max_scaled"] = float(np.max(np.abs(th * (a["grad"] - b["grad"])) / scale))
+    res["meets_1e-6"] = bool(max(res["pred_max_rel"], res["chi2_max_rel"],
+                                 res["grad_max_scaled"]) <= 1e-6)
+    return res
+
+
 def mixed_errors(gna, W, torch, dev, pr, P):
+    """Mixed against FP64 on a chain plan of B points (the same launch shape rules)."""
     model = W.model()
-    res = {}
     outs = {}
     for prec in ("fp64", "mixed"):
         plan = gna.Chain(pr, model, max_batch=P.shape[0], prec=prec, device=dev)
         outs[prec] = {k: v.cpu().numpy() for k, v in plan.eval(P, grad=True, pred=True).items()}
-    a, b = outs["mixed"], outs["fp64"]
-    res["pred_max_rel"] = float(np.max(np.abs(a["pred"] - b["pred"]) / np.abs(b["pred"])))
-    res["chi2_max_rel"] = float(np.max(np.abs(a["chi2"] - b["chi2"]) / np.abs(b["chi2"])))
-    res["chi2_max_abs"] = float(np.max(np.abs(a["chi2"] - b["chi2"])))
-    th = P.cpu().numpy()
-    scale = np.maximum(np.maximum(np.abs(th * b["grad"]), b["chi2"][:, None]), 1.0)
-    res["grad_max_scaled"] = float(np.max(np.abs(th * (a["grad"] - b["grad"])) / scale))
-    return res
+        plan.close()
+    return output_errors(outs["mixed"], outs["fp64"], P.cpu().numpy())
+
+
+def single_point_problem(gna, W, torch, dev, problem_fn, seed):
+    """A single-point geometry with Poisson pseudo-data from this library's
+    FP64 prediction at THETA0."""
+    model = W.model()
+    pr = problem_fn()
+    tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
+    nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
+                  pred=True)["pred"].cpu().numpy()[0]
+    tmp.close()
+    pr["data"] = W.poisson_counts(nu, seed)
+    return pr
+
+
+def fitset_errors(gna, W, torch, dev, problems, P):
+    model = W.model()
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        plan = gna.FitSet(problems, model, prec=prec, device=dev)
+        outs[prec] = {k: v.cpu().numpy() for k, v in plan.eval(P, grad=True, pred=True).items()}
+        plan.close()
+    return output_errors(outs["mixed"], outs["fp64"], P.cpu().numpy())
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_threads():
@@ -491,7 +552,9 @@ def cpu_threads():
 
 
 def cpu_baseline(W, pr_gpu):
-    """The oracle, as it stands, on the scan workload (its own pseudo-data)."""
+    """The oracle, as it stands, on the scan workload (its own pseudo-data): all
+    host threads over the parameter points, then one thread on a 256-point
+    slice of the same scan."""
     import oracle
     model = W.model()
     pr = W.config0()
@@ -507,10 +570,23 @@ def cpu_baseline(W, pr_gpu):
         if time.perf_counter() - t0 > 10.0 or reps >= 500:
             break
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    reps1 = 0
+    while True:
+        oracle.chain(pr, model, P[:256], grad=True, n_threads=1)
+        reps1 += 1
+        if time.perf_counter() - t0 > 5.0:
+            break
+    dt1 = time.perf_counter() - t0
     return {"value": P.shape[0] * reps / dt, "unit": "chi2+grad evals/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{reps} x the full 4096-point scan (1200 points, 240 bins), "
-                      f"{dt:.1f} s, OpenMP over parameter points"}
+            "sample": f"{reps} x the full 4096-point scan (1200 points, 240 bins, FP64), "
+                      f"{dt:.1f} s, OpenMP over parameter points",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": 256 * reps1 / dt1, "unit": "chi2+grad evals/s",
+                              "cores": 1,
+                              "sample": f"{reps1} x the first 256 points of the scan, "
+                                        f"{dt1:.1f} s"}}
 
 
 def main():
@@ -532,9 +608,10 @@ def main():
 
     if args.only:
         o = args.only
-        if o in ("scan", "scan64", "scan_pp", "scan64_pp"):
+        if o in ("scan", "scan64", "scan_pp", "scan64_pp", "scan_rnd", "scan64_rnd"):
             r = bench_scan(gna, W, torch, timer, "fp64" if o.startswith("scan64") else "mixed",
-                           dev, args.steps, args.warmup, share=not o.endswith("_pp"))
+                           dev, args.steps, args.warmup, share=not o.endswith("_pp"),
+                           params=W.config3_random_params() if o.endswith("_rnd") else None)
             log(f"{o}: {r['evals_per_s']:.4g} evals/s kernel {r['kernel_s'] * 1e6:.1f} us "
                 f"shape {r['shape']}")
         elif o in ("pee", "pee64"):
@@ -549,17 +626,22 @@ def main():
         elif o == "chain8":
             log(str(bench_chain_single(gna, W, torch, timer, dev, W.config2, W.SEED + 2,
                                        args.steps, args.prec)))
-        elif o == "fitset":
-            log(str(bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec)))
+        elif o in ("fitset", "fitset1"):
+            r = bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec,
+                             opts={"split_tail": 1, "persistent": 1} if o == "fitset1" else None,
+                             tune=o == "fitset")
+            for k in ("problems", "P", "plan"):
+                r.pop(k)
+            log(f"{o}: {r}")
         return
 
-    log("scan (mixed) ...")
+    log("scan (fp64) ...")
     torch.cuda.synchronize()
-    main_r = bench_scan(gna, W, torch, timer, "mixed", dev, args.steps, args.warmup)
+    main_r = bench_scan(gna, W, torch, timer, "fp64", dev, args.steps, args.warmup)
     B = main_r["P"].shape[0]
-    achieved = main_r["tflops"]
+    v64 = main_r["shape"]["smear_mfma"] + 1
     line = {
-        "metric": "chi2+grad evals/s (batched scan, mixed precision; P_ee evals/s in pee)",
+        "metric": "P_ee evals/s and chi2+grad evals/s, mixed-prec vs FP64 at <=1e-6 rel err",
         "value": main_r["evals_per_s"],
         "unit": "chi2+grad evals/s",
         "n_gpus": 1,
@@ -569,47 +651,84 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "batched scan: 4096 points (64x64 grid in dm2_31 x sin2th13), "
-                               "240 bins x 5-point Gauss-Legendre (1200 points), L=52.5 km, "
-                               "chi2 + 5-parameter adjoint gradient",
+        "config": {"workload": "batched scan in FP64: 4096 points (64x64 grid in dm2_31 x "
+                               "sin2th13), 240 bins x 5-point Gauss-Legendre (1200 points), "
+                               "L=52.5 km, chi2 + 5-parameter adjoint gradient per point",
                    "points": B, "bins": 240, "quadrature_points": 1200, "baselines": 1,
-                   "precision": "mixed (FP64 phases and reduction, FP32 elsewhere, FP64 chi2)",
+                   "precision": "FP64 throughout",
                    "shape": main_r["shape"]},
         "pee_evals_per_s_per_chi2_eval": 1200,
-        "roofline": {"bound": "alu", "kernel": "fused chain kernel (scan)",
-                     "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic(
-                         f"scan_kernel<float,true,512,{main_r['shape']['smear_mfma'] + 1},true>"),
+        "roofline": {"bound": "alu",
+                     "kernel": f"scan_kernel<double,true,512,{v64},true> (FP64, tiles of 16 "
+                               "points with common dm2 share their phases)",
+                     "achieved": main_r["tflops"], "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": main_r["tflops"] / ALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic(f"scan_kernel<double,true,512,{v64},true>"),
                      "kernel_us": main_r["kernel_s"] * 1e6,
                      "kernel_time": "launch period of the timed back-to-back loop (HIP events "
                                     "around all steps / steps)",
                      "event_pair_us": main_r["event_pair_s"] * 1e6,
                      "flops_per_launch": main_r["flops"],
-                     "flop_model": f"shared tiles: {FLOPS_SHARED_PER_ITEM} per (quadrature point, "
-                                   f"baseline) + {FLOPS_SHARED_PER_POINT_BIN} per (point, bin); "
-                                   f"other tiles: {FLOPS_PER_PEE_GRAD_EVAL} per (quadrature "
-                                   f"point, baseline, point)"},
+                     "flop_model": f"executed work: shared tiles {FLOPS_SHARED_PER_ITEM} per "
+                                   f"(quadrature point, baseline) + {FLOPS_SHARED_PER_POINT_BIN} "
+                                   f"per (point, bin); other tiles {FLOPS_PER_PEE_GRAD_EVAL} per "
+                                   f"(quadrature point, baseline, point)",
+                     "per_point_count": {
+                         "flops_per_launch": main_r["pp_flops"],
+                         "achieved": main_r["pp_tflops"],
+                         "frac": main_r["pp_tflops"] / ALU_PEAK_TFLOPS,
+                         "model": f"4096 x 1200 = 4.9e6 P_ee + tangent evaluations x "
+                                  f"{FLOPS_PER_PEE_GRAD_EVAL} flops, the work of a kernel "
+                                  f"that shares nothing (above 1 is impossible for such a "
+                                  f"kernel: the shared tiles skip that work)"}},
     }
+    log("scan (mixed) ...")
+    rmx = bench_scan(gna, W, torch, timer, "mixed", dev, args.steps, args.warmup)
+    vmx = rmx["shape"]["smear_mfma"] + 1
+    line["mixed"] = {"value": rmx["evals_per_s"], "kernel_us": rmx["kernel_s"] * 1e6,
+                     "speedup_over_fp64": rmx["evals_per_s"] / main_r["evals_per_s"],
+                     "kernel": f"scan_kernel<float,true,512,{vmx},true>",
+                     "achieved_tflops": rmx["tflops"], "frac": rmx["tflops"] / ALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic(f"scan_kernel<float,true,512,{vmx},true>"),
+                     "shape": rmx["shape"]}
     if not args.quick:
-        log("scan (fp64) ...")
-        r64 = bench_scan(gna, W, torch, timer, "fp64", dev, args.steps, args.warmup)
-        line["fp64"] = {"value": r64["evals_per_s"], "kernel_us": r64["kernel_s"] * 1e6,
-                        "mixed_speedup": main_r["evals_per_s"] / r64["evals_per_s"],
-                        "shape": r64["shape"]}
-        log("scan with per-point phases ...")
+        log("scan with per-point phases, and a batch of unrelated points ...")
         pp = {}
-        for prec in ("mixed", "fp64"):
+        for prec in ("fp64", "mixed"):
             r = bench_scan(gna, W, torch, timer, prec, dev, args.steps, args.warmup, share=False)
             pp[prec] = {"value": r["evals_per_s"], "kernel_us": r["kernel_s"] * 1e6,
                         "achieved_tflops": r["tflops"], "frac": r["tflops"] / ALU_PEAK_TFLOPS,
                         "shape": r["shape"]}
-        pp["note"] = "every point evaluates its own phases (no_shared_phases=1)"
+        pp["note"] = "the grid with phase sharing switched off (no_shared_phases=1)"
         line["per_point_phases"] = pp
-        log("mixed vs fp64 errors ...")
-        line["mixed_vs_fp64"] = mixed_errors(gna, W, torch, dev, main_r["pr"], main_r["P"])
+        rnd = {}
+        rparams = W.config3_random_params()
+        for prec in ("fp64", "mixed"):
+            r = bench_scan(gna, W, torch, timer, prec, dev, args.steps, args.warmup,
+                           params=rparams)
+            rnd[prec] = {"value": r["evals_per_s"], "kernel_us": r["kernel_s"] * 1e6,
+                         "achieved_tflops": r["tflops"], "frac": r["tflops"] / ALU_PEAK_TFLOPS,
+                         "shape": r["shape"]}
+        rnd["note"] = ("4096 points drawn as THETA0 x U(0.8, 1.2) per parameter: no two "
+                       "points share (dm2_21, dm2_31), so no tile shares its phases")
+        line["random_batch"] = rnd
+        log("mixed vs fp64 errors per output ...")
+        errs = {"definition": {"pred": "max |nu_mixed - nu_fp64| / nu_fp64",
+                               "chi2": "max relative and absolute difference",
+                               "grad": GRAD_ERR_DEF}}
+        errs["scan_grid"] = mixed_errors(gna, W, torch, dev, main_r["pr"], main_r["P"])
+        errs["scan_random"] = mixed_errors(gna, W, torch, dev, main_r["pr"],
+                                           torch.tensor(rparams, device=dev))
+        th1 = torch.tensor(W.THETA0 * np.array([1.01, 0.99, 1.02, 0.97, 1.0]),
+                           device=dev).reshape(1, 5)
+        errs["chain_1pt"] = mixed_errors(
+            gna, W, torch, dev, single_point_problem(gna, W, torch, dev, W.config0, W.SEED), th1)
+        errs["chain_8L"] = mixed_errors(
+            gna, W, torch, dev, single_point_problem(gna, W, torch, dev, W.config2, W.SEED + 2),
+            th1)
+        line["mixed_vs_fp64"] = errs
         log("pee N=1e8 ...")
         pee = {}
         for prec in ("fp64", "mixed"):
@@ -619,6 +738,7 @@ def main():
                           ("mixed", "pee_kernel<float,true,false>")):
             pee[prec]["copy_frac"] = pee[prec]["GBps"] / pee["copy_probe"]["GBps"]
             pee[prec]["traffic"] = measured_traffic(key)
+            pee[prec]["meets_70pct_hbm"] = bool(pee[prec]["hbm_frac"] >= 0.70)
         pee["workload"] = "N=1e8 energies uniform in [1.8, 12] MeV, L=52.5 km, one parameter point"
         line["pee"] = pee
         log("P_ee sweep over N and L ...")
@@ -629,8 +749,21 @@ def main():
         line["chain_8L"] = {p: bench_chain_single(gna, W, torch, timer, dev, W.config2,
                                                   W.SEED + 2, 200, p) for p in ("fp64", "mixed")}
         log("fitset ...")
-        line["fitset"] = {p: bench_fitset(gna, W, torch, timer, dev, 50, p)
-                          for p in ("fp64", "mixed")}
+        fs = {}
+        for p in ("fp64", "mixed"):
+            r = bench_fitset(gna, W, torch, timer, dev, 50, p)
+            problems, P4 = r.pop("problems"), r.pop("P")
+            r.pop("plan").close()
+            fs[p] = r
+            f1 = bench_fitset(gna, W, torch, timer, dev, 50, p,
+                              opts={"split_tail": 1, "persistent": 1}, tune=False)
+            f1.pop("problems"), f1.pop("P"), f1.pop("plan").close()
+            fs[p]["one_launch"] = f1
+        fs["mixed_vs_fp64"] = fitset_errors(gna, W, torch, dev, problems, P4)
+        fs["note"] = ("split_tail=1 in the shape: the point pass plus two tail launches "
+                      "(the autotuner's pick); one_launch: the fused tail in one persistent "
+                      "launch")
+        line["fitset"] = fs
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)
         log("transformation graph, lazy evaluation ...")

@@ -8,17 +8,14 @@ import torch
 
 import oracle
 import workloads as W
-from tests.helpers import FP64_RTOL, grad_error, rel_err, with_data
+from tests.helpers import (FP64_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL, MIXED_PRED_RTOL,
+                           grad_error, rel_err, with_data)
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 MODEL = W.model()
 
-# Mixed-precision bounds (FP32 point pass, bin sums and smearing; FP64 chi^2).
-MIXED_PRED_RTOL = 2e-6
-MIXED_CHI2_RTOL = 1e-5
-MIXED_GRAD_TOL = 1e-4
 
 
 def _plan(problem, B=1, prec="fp64", **opts):
@@ -216,8 +213,16 @@ def test_autograd_function(cfg0):
     assert np.max(np.abs(P.grad.cpu().numpy() - expect) / (np.abs(expect) + 1e-300)) <= 1e-10
 
 
-def test_adjoint_vs_central_differences(cfg0):
-    plan = _plan(cfg0, B=11, smear_mfma=0)
+@pytest.mark.parametrize("cfg", ["cfg0", "cfg2"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adjoint_vs_central_differences(cfg0, cfg2, cfg, prec):
+    """The adjoint gradient against central differences of chi^2 with
+    h = 1e-6 |theta_c| (10 extra points in the same launch).  The differences
+    always come from the FP64 plan: float32 chi^2 noise would swamp a 1e-6
+    step, so the mixed gradient is held to its stated tolerance against the
+    FP64 differences, the FP64 gradient to 1e-6."""
+    pr = cfg0 if cfg == "cfg0" else cfg2
+    plan64 = _plan(pr, B=11, smear_mfma=0)
     th = THETAS[1]
     P = [th]
     for c in range(5):
@@ -226,12 +231,13 @@ def test_adjoint_vs_central_differences(cfg0):
             t = th.copy()
             t[c] += sgn * h
             P.append(t)
-    got = _eval(plan, np.array(P), pred=False)
-    g = got["grad"][0]
+    got = _eval(plan64, np.array(P), pred=False)
+    g = got["grad"][0] if prec == "fp64" else _eval(_plan(pr, prec="mixed"), th, pred=False)["grad"][0]
+    tol = 1e-6 if prec == "fp64" else MIXED_GRAD_TOL
     for c in range(5):
         h = 1e-6 * abs(th[c])
         fd = (got["chi2"][1 + 2 * c] - got["chi2"][2 + 2 * c]) / (2 * h)
-        assert abs(fd - g[c]) * abs(th[c]) <= 1e-6 * max(abs(g[c] * th[c]), got["chi2"][0])
+        assert abs(fd - g[c]) * abs(th[c]) <= tol * max(abs(g[c] * th[c]), got["chi2"][0]), c
 
 
 @pytest.mark.parametrize("mfma", [0, 1])

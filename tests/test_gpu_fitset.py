@@ -7,15 +7,13 @@ import torch
 
 import oracle
 import workloads as W
-from tests.helpers import FP64_RTOL, grad_error, rel_err
+from tests.helpers import (FP64_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL, MIXED_PRED_RTOL,
+                           grad_error, rel_err)
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 MODEL = W.model()
-MIXED_PRED_RTOL = 1e-5
-MIXED_CHI2_RTOL = 1e-4
-MIXED_GRAD_TOL = 1e-3
 
 
 def _with_data(problems):

@@ -5,15 +5,13 @@ import torch
 
 import oracle
 import workloads as W
-from tests.helpers import FP64_RTOL, grad_error, rel_err, with_data
+from tests.helpers import (FP64_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL, MIXED_PRED_RTOL,
+                           grad_error, rel_err, with_data)
 
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 MODEL = W.model()
-MIXED_PRED_RTOL = 2e-6
-MIXED_CHI2_RTOL = 1e-5
-MIXED_GRAD_TOL = 1e-4
 # Geometries with baselines of hundreds of km: the dm2_21 and norm components
 # of the gradient cancel strongly there, and FP32 mu, tangents and smearing
 # (the mixed design) leave ~1e-4 in the scaled metric whichever order the sums

@@ -98,6 +98,14 @@ def config3_params(n_dm=64, n_s13=64):
     return P
 
 
+def config3_random_params(n=4096, seed=SEED + 3):
+    """A batch of the scan's size whose points share nothing: every parameter
+    drawn as THETA0 * U(0.8, 1.2) (so no two points have a common dm2_21 or
+    dm2_31)."""
+    rng = np.random.default_rng(seed)
+    return THETA0 * rng.uniform(0.8, 1.2, (int(n), 5))
+
+
 def config4(n_fits=1024, seed=SEED + 4):
     """Uneven batch: per fit draw n_bins in [50, 2000], GL order in [3, 10],
     n_L in [1, 20] baselines uniform in [1, 1300] km (equal weights), and

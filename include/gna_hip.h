@@ -359,6 +359,25 @@ int gna_plan_autotune(gna_plan* plan, const double* params_dev, int32_t B, doubl
                       int32_t shape_out[7]);
 /* Frees the host-side plan (the caller still owns the workspace). */
 int gna_plan_destroy(gna_plan* plan);
+/*
+ * Recovery (Sec. 5: a computation that fails is restarted from a saved
+ * state): runs the configuration stage again into the plan's workspace from
+ * the description the plan keeps on the host (tables, band of R, data,
+ * launch shape; counters, queue and status word cleared), so a plan whose
+ * evaluation failed or whose workspace was overwritten evaluates as new.
+ * The chosen launch shape is kept.  Synchronizes `stream`.
+ * Errors: GNA_E_INVAL, GNA_E_HIP.
+ */
+int gna_plan_rebuild(gna_plan* plan, void* stream);
+
+/* ---- fault injection (tests of error handling) --------------------------- */
+/* The next `count` HIP status checks inside the library that would succeed
+ * report GNA_E_HIP instead ("injected failure"), so recovery paths can be
+ * exercised from the host while every kernel still runs and exits normally.
+ * count = 0 clears pending injections.  Process-wide.  Errors: GNA_E_INVAL. */
+int gna_debug_inject_hip_errors(int32_t count);
+/* Injected failures not yet consumed. */
+int32_t gna_debug_pending_hip_errors(void);
 
 /* ---- unfused transformations (vector in / vector out) -------------------- */
 /*
@@ -501,6 +520,74 @@ int gna_graph_read(gna_graph* graph, int32_t node, double* host_out, int64_t n, 
 /* Output length of a node, and how many times it has been computed. */
 int gna_graph_node_info(const gna_graph* graph, int32_t node, int64_t* n_out,
                         int64_t* evaluations);
+
+/* ---- graph: host mirrors, target device, formula items, fused nodes ------
+ * Every node output has a host mirror beside its device copy; a copy between
+ * them happens only when the side that is read is stale (Sec. 4.2): reading a
+ * node twice without a change in between copies once, and a node computed on
+ * the CPU is uploaded only when a GPU node or gna_graph_eval needs it.
+ *
+ * Target device (Sec. 4.2: one flag switches where a transformation runs):
+ * GNA_TARGET_GPU (default) or GNA_TARGET_CPU for one node, or node = -1 for
+ * every node that has a CPU form (all but the geometry tables and the fused
+ * chain node, which run on the GPU; asking CPU for one of those fails with
+ * GNA_E_UNSUPPORTED).  A CPU node computes in FP64 on the host with libm,
+ * its inputs brought to the host first.  The flag is the only way a node
+ * runs on the CPU: the library never switches by itself.  Changing the
+ * target does not taint a node.
+ */
+#define GNA_TARGET_GPU 0
+#define GNA_TARGET_CPU 1
+int gna_graph_set_target(gna_graph* graph, int32_t node, int32_t target);
+/* stats[0] = output length, [1] = evaluations, [2] = device-to-host copies,
+ * [3] = host-to-device copies of the node's output, [4] = GPU failures the
+ * node recovered from on the CPU (failover below); *target its target.
+ * (Copies of a geometry's smearing matrix for CPU smearing nodes are counted
+ * on none of the nodes.) */
+int gna_graph_node_stats(const gna_graph* graph, int32_t node, int64_t stats[5],
+                         int32_t* target);
+/* Failover (Sec. 5: the CPU implementation stays available when the GPU
+ * fails), off by default: with on = 1, a GPU node whose kernel or copy
+ * reports GNA_E_HIP is computed by its CPU form instead, the recovery is
+ * counted in stats[4], and the node keeps its GPU target for the next
+ * evaluation.  Nodes without a CPU form (the fused chain) return the error. */
+int gna_graph_set_failover(gna_graph* graph, int32_t on);
+
+/*
+ * Formula items of the Sec. 4.1 probability (OscProb as one transformation
+ * per term, then a weighted sum): over a node's energies E and one baseline,
+ *   item 0: sin^2 phi,  item 1: sin 2phi,  phi = dm2 L / 4E = dm2 (K L) / E,
+ * for pair 0 (dm2_21), 1 (dm2_31) or 2 (dm2_32 = dm2_31 - dm2_21).  The
+ * node reads both splitting variables but is tainted only by those its phase
+ * depends on.
+ */
+int gna_graph_osc_item(gna_graph* graph, int32_t energies, double L_km, int32_t dm21_var,
+                       int32_t dm31_var, int32_t pair, int32_t item, int32_t* node_out);
+/* P_ee = 1 - 4 sum_{i>j} |U_ei|^2 |U_ej|^2 sin^2 phi_ij from the three sin^2
+ * items (pairs 21, 31, 32, same energies) and the mixing variables
+ * sin^2 th12, sin^2 th13: a change of a mixing variable recomputes this node
+ * only. */
+int gna_graph_pee_items(gna_graph* graph, const int32_t sin2_items[3], int32_t s12_var,
+                        int32_t s13_var, int32_t* node_out);
+/* P(alpha -> beta) = delta_ab - 4 sum Re(X_ij) sin^2 phi_ij + 2 sum Im(X_ij)
+ * sin 2phi_ij (the full Sec. 4.1 equation, as gna_prob) from the three sin^2
+ * and the three sin 2phi items and the variables (th12, th13, th23, delta_CP)
+ * [rad]; antineutrino 0 or 1 (delta -> -delta). */
+int gna_graph_prob_items(gna_graph* graph, int32_t alpha, int32_t beta, int32_t antineutrino,
+                         const int32_t angle_vars[4], const int32_t sin2_items[3],
+                         const int32_t sin2phi_items[3], int32_t* node_out);
+/* The fused general probability (gna_prob, FP64, one baseline) as a node:
+ * variables (th12, th13, th23, delta_CP) and (dm2_21, dm2_31). */
+int gna_graph_prob(gna_graph* graph, int32_t energies, double L_km, int32_t alpha, int32_t beta,
+                   int32_t antineutrino, const int32_t angle_vars[4], const int32_t dm_vars[2],
+                   int32_t* node_out);
+/* The fused chain of a geometry (its baselines, quadrature and data; the
+ * chain kernel of gna_chain_eval) as a node with output [6] = (chi^2,
+ * d chi^2 / d theta for theta = the 5 variables (dm2_21, dm2_31, s12, s13,
+ * norm)), in GNA_FP64 or GNA_MIXED: the graph's way to the gradient.  GPU
+ * only.  Domain errors give NaN (the node has no status word). */
+int gna_graph_chain(gna_graph* graph, int32_t points, const int32_t vars[5], int32_t prec,
+                    int32_t* node_out);
 
 #ifdef __cplusplus
 }

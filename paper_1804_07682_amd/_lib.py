@@ -21,6 +21,8 @@ GNA_E_WORKSPACE = -4
 GNA_E_UNSUPPORTED = -5
 GNA_FP64 = 0
 GNA_MIXED = 1
+GNA_TARGET_GPU = 0
+GNA_TARGET_CPU = 1
 
 _dp = C.POINTER(C.c_double)
 _vp = C.c_void_p
@@ -123,6 +125,20 @@ SIGNATURES = {
     "gna_graph_read": (C.c_int, [_GraphP, C.c_int32, _dp, C.c_int64, _vp]),
     "gna_graph_node_info": (C.c_int, [_GraphP, C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]),
+    "gna_graph_set_target": (C.c_int, [_GraphP, C.c_int32, C.c_int32]),
+    "gna_graph_node_stats": (C.c_int, [_GraphP, C.c_int32, C.POINTER(C.c_int64), _i32p]),
+    "gna_graph_osc_item": (C.c_int, [_GraphP, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_pee_items": (C.c_int, [_GraphP, _i32p, C.c_int32, C.c_int32, _i32p]),
+    "gna_graph_prob_items": (C.c_int, [_GraphP, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p,
+                                       _i32p, _i32p]),
+    "gna_graph_prob": (C.c_int, [_GraphP, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                 C.c_int32, _i32p, _i32p, _i32p]),
+    "gna_graph_chain": (C.c_int, [_GraphP, C.c_int32, _i32p, C.c_int32, _i32p]),
+    "gna_graph_set_failover": (C.c_int, [_GraphP, C.c_int32]),
+    "gna_plan_rebuild": (C.c_int, [_PlanP, _vp]),
+    "gna_debug_inject_hip_errors": (C.c_int, [C.c_int32]),
+    "gna_debug_pending_hip_errors": (C.c_int32, []),
 }
 
 _lib = None

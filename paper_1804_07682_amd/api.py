@@ -401,6 +401,11 @@ class _PlanBase:
                                        path, _stream(self.device), s), "gna_plan_autotune")
         return self.shape()
 
+    def rebuild(self):
+        """Run the configuration stage again into the plan's workspace (recovery
+        after a failed evaluation or an overwritten workspace)."""
+        check(load().gna_plan_rebuild(self._plan, _stream(self.device)), "gna_plan_rebuild")
+
     def close(self):
         if self._plan is not None:
             load().gna_plan_destroy(self._plan)
@@ -444,8 +449,10 @@ class Chain(_PlanBase):
         self._plan = plan
         self._eval_fn = lib.gna_chain_eval
 
-    def eval(self, params: torch.Tensor, grad=True, pred=False, out=None):
-        """chi^2 [B] (and grad [B, 5], pred [B, n_bins]) for params [B, 5]."""
+    def eval(self, params: torch.Tensor, grad=True, pred=False, out=None, recover=False):
+        """chi^2 [B] (and grad [B, 5], pred [B, n_bins]) for params [B, 5].
+
+        recover: on a HIP error, rebuild the plan once and evaluate again."""
         _need_cuda(params, "params")
         if params.dim() == 1:
             params = params.reshape(1, 5)
@@ -468,9 +475,13 @@ class Chain(_PlanBase):
                                   or not t.is_contiguous()):
                 raise ValueError(f"out[{nm!r}] must be a contiguous CUDA float64 tensor of "
                                  f">= {n} elements")
-        st = self._eval_fn(self._plan, params.data_ptr(), B, chi2.data_ptr(),
-                           None if g is None else g.data_ptr(),
-                           None if pr is None else pr.data_ptr(), _raw_stream(dev))
+        args = (params.data_ptr(), B, chi2.data_ptr(), None if g is None else g.data_ptr(),
+                None if pr is None else pr.data_ptr(), _raw_stream(dev))
+        st = self._eval_fn(self._plan, *args)
+        if st == _lib.GNA_E_HIP and recover:
+            # restart from the configuration the plan keeps, then evaluate again
+            self.rebuild()
+            st = self._eval_fn(self._plan, *args)
         if st:
             check(st, "gna_chain_eval")
         res = {"chi2": chi2}
@@ -615,6 +626,57 @@ class Graph:
     def chi2(self, nu: int, points: int) -> int:
         return self._id(load().gna_graph_chi2, nu, points)
 
+    PAIRS = {"21": 0, "31": 1, "32": 2, 0: 0, 1: 1, 2: 2}
+    ITEMS = {"sin2": 0, "sin2phi": 1, 0: 0, 1: 1}
+
+    def osc_item(self, energies: int, L_km: float, dm21: int, dm31: int, pair, item="sin2") -> int:
+        """sin^2 phi or sin 2phi of the phase of pair '21' | '31' | '32'."""
+        return self._id(load().gna_graph_osc_item, energies, float(L_km), dm21, dm31,
+                        self.PAIRS.get(pair, pair), self.ITEMS.get(item, item))
+
+    def pee_items(self, sin2_items, s12: int, s13: int) -> int:
+        it = (C.c_int32 * 3)(*sin2_items)
+        return self._id(load().gna_graph_pee_items, it, s12, s13)
+
+    def prob_items(self, alpha, beta, angles, sin2_items, sin2phi_items,
+                   antineutrino=False) -> int:
+        ang = (C.c_int32 * 4)(*angles)
+        s2 = (C.c_int32 * 3)(*sin2_items)
+        t2 = (C.c_int32 * 3)(*sin2phi_items)
+        return self._id(load().gna_graph_prob_items, FLAVOURS[alpha], FLAVOURS[beta],
+                        int(bool(antineutrino)), ang, s2, t2)
+
+    def prob(self, energies: int, L_km: float, alpha, beta, angles, dms,
+             antineutrino=False) -> int:
+        ang = (C.c_int32 * 4)(*angles)
+        dm = (C.c_int32 * 2)(*dms)
+        return self._id(load().gna_graph_prob, energies, float(L_km), FLAVOURS[alpha],
+                        FLAVOURS[beta], int(bool(antineutrino)), ang, dm)
+
+    def chain(self, points: int, variables, prec="fp64") -> int:
+        """Fused chain node: output (chi^2, d chi^2 / d theta[5])."""
+        v = (C.c_int32 * 5)(*variables)
+        return self._id(load().gna_graph_chain, points, v, _prec(prec))
+
+    TARGETS = {"gpu": _lib.GNA_TARGET_GPU, "cpu": _lib.GNA_TARGET_CPU}
+
+    def set_target(self, node, target: str):
+        """Run `node` (None: every node that has a CPU form) on 'cpu' or 'gpu'."""
+        check(load().gna_graph_set_target(self._g, -1 if node is None else int(node),
+                                          self.TARGETS[target]), "gna_graph_set_target")
+
+    def stats(self, node: int):
+        st = (C.c_int64 * 5)()
+        tg = C.c_int32(0)
+        check(load().gna_graph_node_stats(self._g, node, st, C.byref(tg)), "gna_graph_node_stats")
+        return {"n": st[0], "evaluations": st[1], "to_host": st[2], "to_device": st[3],
+                "failovers": st[4],
+                "target": "cpu" if tg.value == _lib.GNA_TARGET_CPU else "gpu"}
+
+    def set_failover(self, on: bool):
+        """Recompute a GPU node on the CPU when it reports a HIP error (off by default)."""
+        check(load().gna_graph_set_failover(self._g, int(bool(on))), "gna_graph_set_failover")
+
     def bind(self):
         nbytes = C.c_size_t(0)
         check(load().gna_graph_workspace_size(self._g, C.byref(nbytes)), "gna_graph_workspace_size")
@@ -670,3 +732,13 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def inject_hip_errors(count: int):
+    """Make the library's next `count` HIP status checks report GNA_E_HIP
+    (tests of the recovery paths; 0 clears)."""
+    check(load().gna_debug_inject_hip_errors(int(count)), "gna_debug_inject_hip_errors")
+
+
+def pending_hip_errors() -> int:
+    return int(load().gna_debug_pending_hip_errors())

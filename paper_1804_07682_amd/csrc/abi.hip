@@ -1,4 +1,5 @@
 // Status codes, error messages and small ABI queries of libgna_hip.so.
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -9,6 +10,11 @@ namespace gna {
 
 static thread_local char g_last_error[512] = "";
 
+// Pending injected failures (gna_debug_inject_hip_errors): each successful
+// HIP status checked by the library while this is positive is reported as a
+// failure instead, and the count goes down by one.
+static std::atomic<int> g_inject_hip{0};
+
 int fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -18,7 +24,13 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int check_hip(hipError_t e, const char* what) {
-  if (e == hipSuccess) return GNA_OK;
+  if (e == hipSuccess) {
+    int n = g_inject_hip.load();
+    while (n > 0 && !g_inject_hip.compare_exchange_weak(n, n - 1)) {
+    }
+    if (n > 0) return fail(GNA_E_HIP, "%s: injected failure (gna_debug_inject_hip_errors)", what);
+    return GNA_OK;
+  }
   return fail(GNA_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
@@ -43,5 +55,14 @@ const char* gna_strerror(int status) {
 }
 
 const char* gna_last_error_message(void) { return gna::g_last_error; }
+
+int gna_debug_inject_hip_errors(int32_t count) {
+  gna::clear_error();
+  if (count < 0) return gna::fail(GNA_E_INVAL, "gna_debug_inject_hip_errors: count %d < 0", count);
+  gna::g_inject_hip.store(count);
+  return GNA_OK;
+}
+
+int32_t gna_debug_pending_hip_errors(void) { return gna::g_inject_hip.load(); }
 
 }  // extern "C"

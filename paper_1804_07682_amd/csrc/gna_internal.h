@@ -145,6 +145,11 @@ struct gna_plan {
   std::vector<gna::SliceDev> slices;   // host copy
   std::vector<int32_t> fwd_order;      // fitset: slices, most diagonals first
   std::vector<double> edges_host;      // concatenated edges
+  // The rest of the configuration, kept on the host so that the
+  // configuration stage can be run again into the same workspace
+  // (gna_plan_rebuild): baselines, weights, data, slice owners.
+  std::vector<double> L_host, wL_host, data_host;
+  std::vector<int32_t> slice_prob_host;
 };
 
 namespace gna {
@@ -177,5 +182,19 @@ size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
 // uploads the tile list when the plan has a workspace).
 int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s);
 std::vector<Shape> shape_candidates(const gna_plan* p);
+
+// Coefficients of P_ee in the all-positive form P = K0 + A cos^2 phi21 +
+// B1 cos^2 phi31 + B2 cos^2 phi32 (Sec. 4.1 with alpha = beta = e):
+// A = 4 s12 (1-s12) (1-s13)^2, B = 4 s13 (1-s13), B1 = B (1-s12), B2 = B s12,
+// K0 = 1 - A - B.  Host code (pee.hip).
+void pee_coefficients(double s12, double s13, double* K0, double* A, double* B1, double* B2);
+
+// Coefficients of the Sec. 4.1 probability for flavours a -> b (0 = e, 1 = mu,
+// 2 = tau): P = delta + sum_t re[t] sin^2 phi_t + im[t] sin 2phi_t over the
+// pairs t = (21, 31, 32), re = -4 Re X, im = 2 Im X, X_ij = V*_ai V_bi V_aj
+// V*_bj, V the PMNS matrix of the angles ang = (th12, th13, th23, delta_CP)
+// (delta -> -delta for antineutrinos).  Host code (prob.hip).
+void prob_coefficients(int a, int b, int anti, const double* ang, double* delta, double re[3],
+                       double im[3]);
 
 }  // namespace gna

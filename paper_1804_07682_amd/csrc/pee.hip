@@ -15,6 +15,17 @@
 #include "gna_math.h"
 
 namespace gna {
+
+void pee_coefficients(double s12, double s13, double* K0, double* A, double* B1, double* B2) {
+  const double c12 = 1.0 - s12, c13 = 1.0 - s13;
+  const double a = 4.0 * s12 * c12 * (c13 * c13);
+  const double b = 4.0 * s13 * c13;
+  *K0 = 1.0 - a - b;
+  *A = a;
+  *B1 = b * c12;
+  *B2 = b * s12;
+}
+
 namespace {
 
 constexpr int kPeeThreads = 256;
@@ -131,14 +142,12 @@ template <class R>
 int run_pee(const double* E, int64_t n, int32_t n_L, const double* L, const double* wL,
             const double* th, void* P, hipStream_t s) {
   PeeArgs<R> a{};
-  const double s12 = th[2], s13 = th[3];
-  const double c12 = 1.0 - s12, c13 = 1.0 - s13;
-  const double A = 4.0 * s12 * c12 * (c13 * c13);
-  const double B = 4.0 * s13 * c13;
-  a.K0 = (R)(1.0 - A - B);
+  double K0, A, B1, B2;
+  pee_coefficients(th[2], th[3], &K0, &A, &B1, &B2);
+  a.K0 = (R)K0;
   a.A = (R)A;
-  a.B1 = (R)(B * c12);
-  a.B2 = (R)(B * s12);
+  a.B1 = (R)B1;
+  a.B2 = (R)B2;
   a.dm21 = th[0];
   a.dm31 = th[1];
   a.dm32 = th[1] - th[0];

@@ -629,6 +629,10 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
                      [&](int32_t a, int32_t b) { return v[a].nd > v[b].nd; });
   }
   p->edges_host = b.edges;
+  p->L_host = b.L;
+  p->wL_host = b.wL;
+  p->data_host = b.data;
+  p->slice_prob_host = b.slice_prob;
   // Chunk cap, scratch and tile capacity for every shape the plan may run.
   if (opts && opts->chunks > 0)
     p->ccap = opts->chunks;
@@ -840,6 +844,21 @@ extern "C" int gna_fitset_eval(gna_plan* plan, const double* params_dev, double*
     return fail(GNA_E_INVAL, "device pointers must be 8-byte aligned");
   return launch_chain(plan, params_dev, plan->n_points, chi2_dev, grad_dev, pred_dev,
                       (hipStream_t)stream);
+}
+
+extern "C" int gna_plan_rebuild(gna_plan* plan, void* stream) {
+  clear_error();
+  if (!plan || !plan->ws) return fail(GNA_E_INVAL, "gna_plan_rebuild: plan is NULL");
+  PlanBuild b;
+  b.p = plan;
+  b.L = plan->L_host;
+  b.wL = plan->wL_host;
+  b.edges = plan->edges_host;
+  b.data = plan->data_host;
+  b.slice_prob = plan->slice_prob_host;
+  const int rc = upload_and_build(b, plan->ws, plan->ws_bytes, (hipStream_t)stream);
+  b.p = nullptr;  // the caller keeps the plan
+  return rc;
 }
 
 extern "C" int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status) {

@@ -14,6 +14,40 @@
 #include "gna_math.h"
 
 namespace gna {
+
+// PMNS matrix V[flavour][mass state] = R23 U13(delta) R12.
+static void pmns_matrix(double th12, double th13, double th23, double dcp,
+                        std::complex<double> V[3][3]) {
+  using C = std::complex<double>;
+  const double c12 = std::cos(th12), s12 = std::sin(th12);
+  const double c13 = std::cos(th13), s13 = std::sin(th13);
+  const double c23 = std::cos(th23), s23 = std::sin(th23);
+  const C ep = std::polar(1.0, dcp), em = std::polar(1.0, -dcp);
+  V[0][0] = C(c12 * c13);
+  V[0][1] = C(s12 * c13);
+  V[0][2] = s13 * em;
+  V[1][0] = -s12 * c23 - c12 * s23 * s13 * ep;
+  V[1][1] = c12 * c23 - s12 * s23 * s13 * ep;
+  V[1][2] = C(s23 * c13);
+  V[2][0] = s12 * s23 - c12 * c23 * s13 * ep;
+  V[2][1] = -c12 * s23 - s12 * c23 * s13 * ep;
+  V[2][2] = C(c23 * c13);
+}
+
+void prob_coefficients(int a, int b, int anti, const double* ang, double* delta, double re[3],
+                       double im[3]) {
+  std::complex<double> V[3][3];
+  pmns_matrix(ang[0], ang[1], ang[2], anti ? -ang[3] : ang[3], V);
+  *delta = (a == b) ? 1.0 : 0.0;
+  const int pi[3] = {1, 2, 2}, pj[3] = {0, 0, 1};  // pairs i > j: (2,1), (3,1), (3,2)
+  for (int t = 0; t < 3; ++t) {
+    const int i = pi[t], j = pj[t];
+    const std::complex<double> x = std::conj(V[a][i]) * V[b][i] * V[a][j] * std::conj(V[b][j]);
+    re[t] = -4.0 * x.real();
+    im[t] = 2.0 * x.imag();
+  }
+}
+
 namespace {
 
 constexpr int kProbThreads = 256;
@@ -53,42 +87,21 @@ __global__ void __launch_bounds__(kProbThreads)
     P[i] = prob_eval<R>(a, __builtin_nontemporal_load(E + i));
 }
 
-// PMNS matrix V[flavour][mass state] = R23 U13(delta) R12.
-void pmns_matrix(double th12, double th13, double th23, double dcp, std::complex<double> V[3][3]) {
-  using C = std::complex<double>;
-  const double c12 = std::cos(th12), s12 = std::sin(th12);
-  const double c13 = std::cos(th13), s13 = std::sin(th13);
-  const double c23 = std::cos(th23), s23 = std::sin(th23);
-  const C ep = std::polar(1.0, dcp), em = std::polar(1.0, -dcp);
-  V[0][0] = C(c12 * c13);
-  V[0][1] = C(s12 * c13);
-  V[0][2] = s13 * em;
-  V[1][0] = -s12 * c23 - c12 * s23 * s13 * ep;
-  V[1][1] = c12 * c23 - s12 * s23 * s13 * ep;
-  V[1][2] = C(s23 * c13);
-  V[2][0] = s12 * s23 - c12 * c23 * s13 * ep;
-  V[2][1] = -c12 * s23 - s12 * c23 * s13 * ep;
-  V[2][2] = C(c23 * c13);
-}
-
 int g_cus = 0;
 
 template <class R>
 int run_prob(const double* E, int64_t n, int a, int b, int nL, const double* L, const double* wL,
              const double* ang, const double* dm, int anti, void* P, hipStream_t s) {
-  std::complex<double> V[3][3];
-  pmns_matrix(ang[0], ang[1], ang[2], anti ? -ang[3] : ang[3], V);
+  double delta, re[3], im[3];
+  prob_coefficients(a, b, anti, ang, &delta, re, im);
   ProbArgs<R> k{};
-  k.delta = (R)(a == b ? 1.0 : 0.0);
-  const int pi[3] = {1, 2, 2}, pj[3] = {0, 0, 1};  // pairs i > j: (2,1), (3,1), (3,2)
+  k.delta = (R)delta;
   k.dm[0] = dm[0];
   k.dm[1] = dm[1];
   k.dm[2] = dm[1] - dm[0];
   for (int t = 0; t < 3; ++t) {
-    const int i = pi[t], j = pj[t];
-    const std::complex<double> x = std::conj(V[a][i]) * V[b][i] * V[a][j] * std::conj(V[b][j]);
-    k.re[t] = (R)(-4.0 * x.real());
-    k.im[t] = (R)(2.0 * x.imag());
+    k.re[t] = (R)re[t];
+    k.im[t] = (R)im[t];
   }
   k.n_L = nL;
   for (int r = 0; r < nL; ++r) {

@@ -216,6 +216,16 @@ def test_unfused_transforms_validate_on_the_host(lib):
     assert lib.gna_gl_nodes(5, None, w.ctypes.data_as(dp)) == -1
 
 
+def test_fault_injection_counter(lib):
+    """Injected HIP failures are a host-side counter (no HIP call here)."""
+    assert lib.gna_debug_inject_hip_errors(3) == 0
+    assert lib.gna_debug_pending_hip_errors() == 3
+    assert lib.gna_debug_inject_hip_errors(-1) == -1
+    assert lib.gna_debug_pending_hip_errors() == 3
+    assert lib.gna_debug_inject_hip_errors(0) == 0
+    assert lib.gna_debug_pending_hip_errors() == 0
+
+
 def test_binding_rejects_short_host_arrays(lib):
     """The C side reads n_L weights and n_bins data values: the binding refuses
     vectors of any other length before the call (no GPU needed)."""

@@ -50,3 +50,46 @@ def test_graph_configuration_and_validation(gna):
     with pytest.raises(gna.GnaError):
         g.set(norm, float("nan"))
     g.close()
+
+
+def test_graph_items_targets_and_fused_nodes_configure(gna):
+    """Formula items, the fused probability and chain nodes, the target flag
+    and the copy counters, before binding (host only)."""
+    g = gna.Graph("cpu")
+    pr = W.problem(W.uniform_edges(24), 3, [52.5])
+    pr["data"] = [1.0] * 24
+    v = [g.variable(nm, x) for nm, x in zip(("dm21", "dm31", "s12", "s13", "norm"), W.THETA0)]
+    ang = [g.variable(nm, x) for nm, x in zip(("th12", "th13", "th23", "dcp"),
+                                              (0.58, 0.15, 0.85, 1.2))]
+    pts = g.points(pr, W.model())
+    s2 = [g.osc_item(pts, 52.5, v[0], v[1], p) for p in ("21", "31", "32")]
+    t2 = [g.osc_item(pts, 52.5, v[0], v[1], p, "sin2phi") for p in ("21", "31", "32")]
+    pee = g.pee_items(s2, v[2], v[3])
+    prob = g.prob_items("mu", "e", ang, s2, t2, antineutrino=True)
+    fused = g.prob(pts, 52.5, "e", "tau", ang, v[:2])
+    chain = g.chain(pts, v, "mixed")
+    assert g.info(pee)["n"] == 72 and g.info(prob)["n"] == 72 and g.info(fused)["n"] == 72
+    assert g.info(chain)["n"] == 6
+    st = g.stats(pee)
+    assert st == {"n": 72, "evaluations": 0, "to_host": 0, "to_device": 0, "failovers": 0,
+                  "target": "gpu"}
+    g.set_target(pee, "cpu")
+    assert g.stats(pee)["target"] == "cpu"
+    g.set_target(None, "cpu")
+    assert g.stats(prob)["target"] == "cpu" and g.stats(chain)["target"] == "gpu"
+    assert g.stats(pts)["target"] == "gpu"
+    with pytest.raises(gna.GnaError):
+        g.set_target(chain, "cpu")      # the fused chain runs on the GPU only
+    with pytest.raises(gna.GnaError):
+        g.set_target(pts, "cpu")        # a configuration table
+    with pytest.raises(KeyError):
+        g.set_target(pee, "tpu")
+    with pytest.raises(gna.GnaError):
+        g.pee_items([s2[0], s2[2], s2[1]], v[2], v[3])    # pairs out of order
+    with pytest.raises(gna.GnaError):
+        g.prob_items("e", "mu", ang, s2, s2)              # sin^2 where sin 2phi is needed
+    with pytest.raises(gna.GnaError):
+        g.osc_item(pts, -1.0, v[0], v[1], "21")           # negative baseline
+    with pytest.raises(gna.GnaError):
+        g.chain(pts, v[:4] + [99], "fp64")                # no such variable
+    g.close()

@@ -6,7 +6,7 @@
 // cos^2 of each phase, so one sin^2 polynomial per phase is evaluated
 // (cos^2 = 1 - sin^2 >= 1/2 on the reduced argument).  Phases and their
 // reduction are FP64 in both modes; q = KL / E comes from a refined
-// reciprocal (correctly rounded in FP64 mode, ~2 ulp in mixed mode).
+// reciprocal (~2 ulp), see pee_eval.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -39,15 +39,38 @@ struct PeeArgs {
   R w[kMaxBaselines];
 };
 
+// cos^2 phi in FP64 with the short sin^2 kernel (see pee_eval).
+__device__ __forceinline__ double cos2_phase_short(double phi) {
+  bool odd;
+  const double r = reduce_pio2(phi, odd);
+  const double s2 = sin2_kernel_short(r);
+  return odd ? s2 : 1.0 - s2;
+}
+
+template <class R>
+__device__ __forceinline__ R cos2_stream(double phi) {
+  if constexpr (sizeof(R) == 8)
+    return cos2_phase_short(phi);
+  else
+    return cos2_phase<R>(phi);
+}
+
+// In both modes q = (K L) * (1/E) comes from the refined reciprocal without
+// the quotient's correction step (within 2 ulp), and FP64 takes the short
+// sin^2 kernel: this kernel streams from HBM and its time is set by its
+// vector instruction count as much as by memory, and the two approximations
+// together move P by at most a few 1e-13 relative (at 1300 km, where phases
+// reach 2e3 rad), inside the 1e-12 FP64 target.  The fused chain kernels
+// keep the correctly rounded phase and the full polynomials.
 template <class R, bool ONE_L>
 __device__ __forceinline__ R pee_eval(const PeeArgs<R>& a, double E) {
   R acc = R(0);
   const int nL = ONE_L ? 1 : a.n_L;
   for (int r = 0; r < nL; ++r) {
-    const double q = (sizeof(R) == 8) ? phase_per_ev2(a.KL[r], E) : phase_per_ev2_fast(a.KL[r], E);
-    const R c21 = cos2_phase<R>(a.dm21 * q);
-    const R c31 = cos2_phase<R>(a.dm31 * q);
-    const R c32 = cos2_phase<R>(a.dm32 * q);
+    const double q = phase_per_ev2_fast(a.KL[r], E);
+    const R c21 = cos2_stream<R>(a.dm21 * q);
+    const R c31 = cos2_stream<R>(a.dm31 * q);
+    const R c32 = cos2_stream<R>(a.dm32 * q);
     R p = rfma_t<R>(a.A, c21, a.K0);
     p = rfma_t<R>(a.B1, c31, p);
     p = rfma_t<R>(a.B2, c32, p);

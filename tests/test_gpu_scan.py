@@ -245,3 +245,27 @@ def test_scan_autotune_keeps_results(cfg0, sharing_batch, tmp_path):
     again = gna.Chain(cfg0, MODEL, max_batch=64, device=DEV).autotune(Pt, reps=2,
                                                                        cache_path=cache)
     assert again == shape
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_scan_kernel_variants_match_oracle(cfg0, variant, prec):
+    """Every register variant of the scan kernel (2, 3 or 4 wavefronts per
+    SIMD), on shared tiles (a grid in s13) and per-point tiles (points that
+    share nothing), the 240-bin geometry and an odd one."""
+    import paper_1804_07682_amd as gna
+    odd = with_data(W.problem(W.uniform_edges(83), 4, [30.0, 52.5, 700.0], [0.2, 0.5, 0.3],
+                              n_sub=2), MODEL, 5)
+    for pr, P in ((cfg0, W.config3_params(3, 16)), (cfg0, W.config3_random_params(40)),
+                  (odd, W.config3_params(3, 7))):
+        plan = gna.Chain(pr, MODEL, max_batch=P.shape[0], prec=prec,
+                         opts={"smear_mfma": variant}, device=DEV)
+        assert plan.shape()["smear_mfma"] == variant
+        got = _eval(plan, P)
+        ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
+        long_l = max(pr["L"]) > 100
+        tol = (FP64_RTOL,) * 3 if prec == "fp64" else \
+            (MIXED_PRED_RTOL, MIXED_CHI2_RTOL, MIXED_GRAD_TOL_LONG_L if long_l else MIXED_GRAD_TOL)
+        assert np.max(rel_err(got["pred"], ref["nu"])) <= tol[0]
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= tol[1]
+        assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= tol[2]

@@ -348,9 +348,10 @@ def bench_fitset(gna, W, torch, timer, dev, steps, prec, opts=None, tune=True):
     wall, _, _ = timer.run(lambda: plan.eval(P, grad=True), steps, 3)
     kmean = timer.period
     shape = plan.shape()
-    # A split tail is the point pass plus two tail launches; otherwise one launch.
+    # A split tail is the point pass plus two tail launches; the fused and the
+    # queued tails are one launch.
     return {"fits_per_s": len(problems) * steps / wall, "kernel_ms": kmean * 1e3,
-            "launches": 3 if shape["split_tail"] else 1, "shape": shape,
+            "launches": 3 if shape["split_tail"] == 1 else 1, "shape": shape,
             "problems": problems, "plan": plan, "P": P}
 
 
@@ -626,9 +627,10 @@ def main():
         elif o == "chain8":
             log(str(bench_chain_single(gna, W, torch, timer, dev, W.config2, W.SEED + 2,
                                        args.steps, args.prec)))
-        elif o in ("fitset", "fitset1"):
-            r = bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec,
-                             opts={"split_tail": 1, "persistent": 1} if o == "fitset1" else None,
+        elif o in ("fitset", "fitset1", "fitsetq"):
+            opts = {"fitset1": {"split_tail": 1, "persistent": 1},
+                    "fitsetq": {"split_tail": 3, "persistent": 1}}.get(o)
+            r = bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec, opts=opts,
                              tune=o == "fitset")
             for k in ("problems", "P", "plan"):
                 r.pop(k)
@@ -755,14 +757,17 @@ def main():
             problems, P4 = r.pop("problems"), r.pop("P")
             r.pop("plan").close()
             fs[p] = r
-            f1 = bench_fitset(gna, W, torch, timer, dev, 50, p,
-                              opts={"split_tail": 1, "persistent": 1}, tune=False)
-            f1.pop("problems"), f1.pop("P"), f1.pop("plan").close()
-            fs[p]["one_launch"] = f1
+            for tag, sp in (("one_launch_queued_tail", 3), ("one_launch_fused_tail", 1)):
+                f1 = bench_fitset(gna, W, torch, timer, dev, 50, p,
+                                  opts={"split_tail": sp, "persistent": 1}, tune=False)
+                f1.pop("problems"), f1.pop("P"), f1.pop("plan").close()
+                fs[p][tag] = f1
         fs["mixed_vs_fp64"] = fitset_errors(gna, W, torch, dev, problems, P4)
-        fs["note"] = ("split_tail=1 in the shape: the point pass plus two tail launches "
-                      "(the autotuner's pick); one_launch: the fused tail in one persistent "
-                      "launch")
+        fs["note"] = ("the autotuned shape (split_tail 1: the point pass plus two tail "
+                      "launches; 2: the queued tail in one persistent launch), and two "
+                      "one-launch shapes with the automatic lane counts: the queued tail "
+                      "(tail slices as queue items after the point tiles) and the fused "
+                      "tail (each fit's tail in the work-group of its last tile)")
         line["fitset"] = fs
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)

@@ -261,7 +261,11 @@ typedef struct gna_problem {
  *                  finishes the fit's last tile; 2: the point pass only
  *                  stores bin sums, and two more launches run the tails of
  *                  all fits with one wavefront per 64-row slice, then add
- *                  each fit's partials in a fixed order.
+ *                  each fit's partials in a fixed order; 3: queued tail,
+ *                  the same tail work as queue items after the point tiles
+ *                  of one persistent launch (a slice waits for its own fit's
+ *                  tiles; implies persistent = 1; same results as 2, bit for
+ *                  bit).
  */
 typedef struct gna_launch_opts {
   int32_t threads;
@@ -343,7 +347,8 @@ int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
  * of one evaluation.  shared_phases is 1 when the MFMA kernel lets tiles with
  * common (dm2_21, dm2_31) share their phases: the plan allows it
  * (no_shared_phases = 0) and the shape asks for it (the autotuner tries
- * both).  split_tail is 1 when a fitset runs its tails in separate launches. */
+ * both).  split_tail is 1 when a fitset runs its tails in separate launches,
+ * 2 when it queues them in its one persistent launch. */
 int gna_plan_shape(const gna_plan* plan, int32_t shape_out[7], int64_t* n_tiles);
 /*
  * Project-written autotuner: times each candidate launch shape of this plan

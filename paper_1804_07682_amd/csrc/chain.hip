@@ -154,7 +154,7 @@ struct BaseLds {
   double w[kMaxBaselines];   // w_r
 };
 
-template <class R, bool GRAD, bool SPLIT>
+template <class R, bool GRAD, bool SPLIT, bool QUEUED = false>
 __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L, BaseLds& bl) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
@@ -269,7 +269,10 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   const int nb = pd.n_bins;
   if (SPLIT) {
     // Split tail: every tile leaves its partial sums in the scratch region;
-    // the tail kernels read them after this launch.
+    // the tail kernels read them after this launch.  Queued tail: the tile
+    // then counts itself done for its fit, releasing its sums at agent scope
+    // (every wavefront's stores acknowledged first, one L2 write-back by the
+    // release-ordered increment), for the tail items of the same launch.
     R* sc = a.scratch + pd.scratch_off;
     if (g == 0 && lb < pd.bins_per_tile && j < nb) {
       sc[(int64_t)(td.chunk * 5) * nb + j] = mu;
@@ -277,6 +280,13 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
 #pragma unroll
         for (int c = 0; c < 4; ++c) sc[(int64_t)(td.chunk * 5 + 1 + c) * nb + j] = J[c];
       }
+    }
+    if (QUEUED) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_fetch_add(&a.counters[td.point], 1u, __ATOMIC_ACQ_REL,
+                               __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
@@ -592,15 +602,15 @@ __device__ __forceinline__ void band_block_dot(const R* __restrict__ Bv, const S
   }
 }
 
-template <class R, bool GRAD>
-__global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
+// One slice of the tail of fit slice_prob[item]: its 64 rows of nu = norm R mu0
+// (and R J0 with the gradient), their chi^2 terms and gradient seeds, summed
+// over the wavefront; lane 0 stores the six partials at part[item].  Shared by
+// the split tail and the queued tail, whose arguments (A) carry the same
+// fields, so both give the same bits.
+template <class R, bool GRAD, class A>
+__device__ __forceinline__ void slice_tail(const A& a, int64_t item, int lane, R* win) {
   constexpr int NC = GRAD ? 5 : 1;
   constexpr int WD = kWinDiag<R, GRAD>;
-  __shared__ R win_all[kTailWaves][NC * (kSlice + WD + kTailBatch<R>)];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
-  if (idx >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
-  const int64_t item = a.order[idx];
   const int f = a.slice_prob[item];
   const ProbDev pd = a.probs[f];
   const int s = (int)(item - pd.slice_off);
@@ -609,7 +619,7 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
   const double norm = a.params[5 * (int64_t)f + 4];
   // acc[0] = (R mu0)_i and, with the gradient, acc[1 + c] = (R J0)_ic.
   R acc[NC];
-  band_block_dot<R, NC, WD>(a.Rv, a.slices[item], s, lane, nb, win_all[wave], sc, C, acc);
+  band_block_dot<R, NC, WD>(a.Rv, a.slices[item], s, lane, nb, win, sc, C, acc);
   const int i = s * kSlice + lane;
   double chi = 0.0;
   double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -644,14 +654,23 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
   }
 }
 
-// One wavefront per fit: lane s takes slice s (a fit has at most
-// kMaxBins / 64 = 64 of them), and the butterfly sums are fixed-order.
 template <class R, bool GRAD>
-__global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs<R> a) {
-  static_assert(kMaxBins <= kSlice * kWave, "one lane per slice");
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R> a) {
+  constexpr int NC = GRAD ? 5 : 1;
+  constexpr int WD = kWinDiag<R, GRAD>;
+  __shared__ R win_all[kTailWaves][NC * (kSlice + WD + kTailBatch<R>)];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
-  const int f = blockIdx.x * kTailWaves + wave;
-  if (f >= a.n_fits) return;
+  const int64_t idx = (int64_t)blockIdx.x * kTailWaves + wave;
+  if (idx >= a.n_items) return;  // whole wavefronts leave; no work-group barrier below
+  slice_tail<R, GRAD>(a, a.order[idx], lane, win_all[wave]);
+}
+
+// The chi^2 and gradient of fit f from its slice partials: lane s takes slice
+// s (a fit has at most kMaxBins / 64 = 64 of them), and the butterfly sums
+// are fixed-order.  Shared by the split and the queued tail.
+template <class R, bool GRAD, class A>
+__device__ __forceinline__ void fit_final(const A& a, int f, int lane) {
+  static_assert(kMaxBins <= kSlice * kWave, "one lane per slice");
   const ProbDev pd = a.probs[f];
   const double* th = a.params + 5 * (int64_t)f;
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -673,6 +692,120 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs
 #pragma unroll
     for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * v[1 + c];
     gp[4] = bad ? NAN : v[5];
+  }
+}
+
+// One wavefront per fit.
+template <class R, bool GRAD>
+__global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs<R> a) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  const int f = blockIdx.x * kTailWaves + wave;
+  if (f >= a.n_fits) return;
+  fit_final<R, GRAD>(a, f, lane);
+}
+
+// ---- queued tail (uneven batches, one persistent launch) --------------------
+// The queue holds the point tiles (longest first), then the tail work of
+// tail_fwd as items of one slice per wavefront, longest slices first.  A
+// wavefront that takes a slice of fit f waits until f's point tiles have all
+// counted themselves done: every tile index was handed out before any tail
+// index, and the work-groups holding tiles wait on nothing, so the wait ends
+// (it is bounded all the same: past kSpinLimit sleeps the wavefront gives up
+// and latches kSpinTimeout).  The wavefront that finishes a fit's last slice
+// adds the fit's slice partials as tail_final does and clears the fit's two
+// counters for the next evaluation.  Same operations in the same order as the
+// split tail, so the results are the same bits.
+constexpr uint32_t kSpinLimit = 1u << 20;  // >= 1M sleeps of 128 clocks: tens of ms at least
+
+template <class R, bool GRAD>
+__device__ void queued_slice(const ChainArgs<R>& a, int64_t idx, int lane, R* win) {
+  const int64_t item = a.order[idx];
+  const int f = a.slice_prob[item];
+  const uint32_t need = (uint32_t)(a.probs[f].n_bin_blocks * a.probs[f].C);
+  uint32_t late = 0;
+  if (lane == 0) {
+    for (uint32_t spin = 0;; ++spin) {
+      if (__hip_atomic_load(&a.counters[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)
+        break;
+      if (spin >= kSpinLimit) {
+        late = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  late = __shfl(late, 0, kWave);
+  if (late)
+    __hip_atomic_fetch_or(a.status, (uint32_t)kSpinTimeout, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the fit's bin sums
+  slice_tail<R, GRAD>(a, item, lane, win);
+  uint32_t last = 0;
+  if (lane == 0) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the partials, before the count
+    const uint32_t prev = __hip_atomic_fetch_add(&a.slice_done[f], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    last = (prev + 1 == (uint32_t)a.probs[f].n_slices) ? 1u : 0u;
+  }
+  last = __shfl(last, 0, kWave);
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other slices' partials
+  fit_final<R, GRAD>(a, f, lane);
+  // Every wavefront of this fit has passed its wait and counted its slice:
+  // the fit's counters start the next evaluation at zero.
+  if (lane == 0) {
+    a.counters[f] = 0u;
+    a.slice_done[f] = 0u;
+  }
+}
+
+// Window LDS of one wavefront of the queued tail.
+template <class R, bool GRAD>
+constexpr int kQueuedWin = (GRAD ? 5 : 1) * (kSlice + kWinDiag<R, GRAD> + kTailBatch<R>);
+
+}  // namespace
+
+size_t queued_lds_bytes(const gna_plan* p, const Shape& sh) {
+  const size_t per_wave = p->prec == GNA_FP64 ? sizeof(double) * kQueuedWin<double, true>
+                                              : sizeof(float) * kQueuedWin<float, true>;
+  return (size_t)(sh.threads / kWave) * per_wave;
+}
+
+namespace {
+
+template <class R, bool GRAD>
+__global__ void __launch_bounds__(1024) chain_queued_kernel(ChainArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ BaseLds bl;
+  __shared__ uint32_t next;
+  const int nw = blockDim.x / kWave;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
+  TileLds L{lds_raw, (int)blockDim.x, 0, 1};
+  const int64_t n_tail = (a.n_slices + nw - 1) / nw;
+  for (;;) {
+    if (threadIdx.x == 0)
+      next = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t t = next;
+    __syncthreads();
+    if (t >= a.n_tiles + n_tail) break;
+    if (t < a.n_tiles) {
+      process_tile<R, GRAD, true, true>(a, t, L, bl);
+    } else {
+      const int64_t idx = (t - a.n_tiles) * nw + wave;
+      if (idx < a.n_slices)
+        queued_slice<R, GRAD>(a, idx, lane,
+                              reinterpret_cast<R*>(lds_raw) + (size_t)wave * kQueuedWin<R, GRAD>);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(&a.queue[1], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (done + 1 == gridDim.x) {
+      a.queue[0] = 0u;
+      a.queue[1] = 0u;
+    }
   }
 }
 
@@ -736,6 +869,30 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   return check_hip(hipGetLastError(), "chain_kernel launch");
 }
 
+template <class R, bool GRAD>
+int launch_queued(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
+  const Shape& sh = p->shape;
+  auto kern = chain_queued_kernel<R, GRAD>;
+  gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
+  if (!lc.ready) {
+    lc.lds = queued_lds_bytes(p, sh);
+    lc.occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&lc.occ, kern, sh.threads, lc.lds) !=
+            hipSuccess ||
+        lc.occ < 1)
+      lc.occ = 1;
+    lc.share = 0;
+    lc.rlds = 0;
+    lc.ready = 1;
+  }
+  const int64_t grid = std::min<int64_t>(a.n_tiles + (a.n_slices + sh.threads / kWave - 1) /
+                                                         (sh.threads / kWave),
+                                         (int64_t)lc.occ * p->cu_count);
+  if (grid < 1) return GNA_OK;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lc.lds, s, a);
+  return check_hip(hipGetLastError(), "chain_queued_kernel launch");
+}
+
 template <class R>
 int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
              double* pred, hipStream_t s) {
@@ -771,6 +928,14 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
   a.grad = grad;
   a.pred = pred;
   const bool pers = p->shape.persistent != 0;
+  if (p->shape.split == 2) {
+    a.slice_prob = (const int32_t*)(w + L.slice_prob);
+    a.order = (const int32_t*)(w + L.fwd_order);
+    a.n_slices = p->total_slices;
+    a.part = (double*)(w + L.tailpart);
+    a.slice_done = (uint32_t*)(w + L.counters) + p->n_points;
+    return grad ? launch_queued<R, true>(p, a, s) : launch_queued<R, false>(p, a, s);
+  }
   if (p->shape.split) {
     int rc;
     if (grad)

@@ -83,9 +83,19 @@ struct ChainArgs {
   double* chi2;
   double* grad;
   double* pred;
+  // Queued tail (uneven batches, one launch): the fit of each slice, the
+  // slices in queue order, the per-slice partial sums and the per-fit count
+  // of finished slices (counters holds the per-fit count of finished tiles).
+  const int32_t* slice_prob;
+  const int32_t* order;
+  int64_t n_slices;
+  double* part;
+  uint32_t* slice_done;
 };
 
-enum StatusBits : uint32_t { kBadMixing = 1u, kBadPrediction = 2u };
+// kSpinTimeout: a queued tail waited longer than its bound for a fit's point
+// tiles (its results are not valid).
+enum StatusBits : uint32_t { kBadMixing = 1u, kBadPrediction = 2u, kSpinTimeout = 4u };
 
 // ---- host-side plan ---------------------------------------------------------
 enum PlanKind { kChain = 0, kFitset = 1 };
@@ -99,7 +109,11 @@ struct Layout {
 struct Shape {
   int threads = 256, G = 1, C = 1, persistent = 0, mfma = 0;
   int share = 1;  // MFMA kernel: tiles with common dm2 share their phases (if the plan allows)
-  int split = 0;  // uneven batch: the tail runs in its own launches, wide over the GPU
+  // Uneven batch: 0 = each fit's tail in the work-group that finishes its
+  // last tile; 1 = the tails in two more launches, wide over the GPU;
+  // 2 = queued tail: the same wide tail work as queue items after the point
+  // tiles, in the one persistent launch.
+  int split = 0;
 };
 
 }  // namespace gna
@@ -178,6 +192,8 @@ struct ChainLds {
 };
 ChainLds chain_lds(const gna_plan* p, const Shape& sh);
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
+// Dynamic LDS of the queued-tail kernel: one staging window per wavefront.
+size_t queued_lds_bytes(const gna_plan* p, const Shape& sh);
 // Sets the per-problem tiling of `sh` (and, for a fitset, rebuilds and
 // uploads the tile list when the plan has a workspace).
 int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s);

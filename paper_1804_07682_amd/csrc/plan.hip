@@ -305,7 +305,8 @@ ChainLds chain_lds(const gna_plan* p, const Shape& sh) {
 }
 
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
-  if (sh.split) return 0;  // the point pass alone keeps nothing in LDS
+  if (sh.split == 1) return 0;  // the point pass alone keeps nothing in LDS
+  if (sh.split == 2) return queued_lds_bytes(p, sh);  // the tail items' windows
   return chain_lds(p, sh).bytes;
 }
 
@@ -368,7 +369,8 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
         // Beyond one point per lane the lanes split (point, baseline) items.
         if (C > p->ccap || C > ppb * nL / G + 1) continue;
         for (int pers = 0; pers <= 1; ++pers)
-          for (int split = 0; split <= (p->kind == kFitset ? 1 : 0); ++split) {
+          for (int split = 0; split <= (p->kind == kFitset ? 2 : 0); ++split) {
+            if (split == 2 && !pers) continue;  // the queued tail is a persistent launch
             Shape sh;
             sh.threads = t;
             sh.G = G;
@@ -401,6 +403,8 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
   if (sh.C < 1) return fail(GNA_E_INVAL, "chunks = %d invalid", sh.C);
   if (sh.split && p->kind != kFitset)
     return fail(GNA_E_UNSUPPORTED, "a split tail needs a fitset plan");
+  if (sh.split == 2 && !sh.persistent)
+    return fail(GNA_E_UNSUPPORTED, "a queued tail needs the persistent launch");
   if (sh.mfma && !(p->kind == kChain && scan_supported(p)))
     return fail(GNA_E_UNSUPPORTED, "MFMA smearing needs a chain plan with n_bins <= 256");
   if (!sh.mfma && chain_lds_bytes(p, sh) > p->lds_limit)
@@ -507,7 +511,9 @@ void compute_layout(gna_plan* p, PlanBuild& b) {
   L.gl = take(16 * kGLTable);
   L.Rv = take(rs * p->total_band);
   L.scratch = take(rs * p->scratch_elems);
-  L.counters = take(4 * (size_t)std::max(p->n_points, 1));
+  // Chain: one completion counter per point.  Fitset: per fit, the finished
+  // tiles, then (queued tail) the finished slices.
+  L.counters = take(4 * (size_t)(p->kind == kFitset ? 2 : 1) * std::max(p->n_points, 1));
   L.queue = take(16);
   L.status = take(16);
   L.Rdense = take(p->kind == kChain ? scan_dense_bytes(p) : 0);
@@ -555,10 +561,10 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       return fail(GNA_E_INVAL, "opts.smear_mfma = %d not in -1..3", opts->smear_mfma);
     if (opts->no_shared_phases < 0 || opts->no_shared_phases > 1)
       return fail(GNA_E_INVAL, "opts.no_shared_phases = %d not 0/1", opts->no_shared_phases);
-    if (opts->split_tail < 0 || opts->split_tail > 2)
-      return fail(GNA_E_INVAL, "opts.split_tail = %d not in 0..2", opts->split_tail);
-    if (opts->split_tail == 2 && kind != kFitset)
-      return fail(GNA_E_INVAL, "opts.split_tail = 2 needs a fitset plan");
+    if (opts->split_tail < 0 || opts->split_tail > 3)
+      return fail(GNA_E_INVAL, "opts.split_tail = %d not in 0..3", opts->split_tail);
+    if (opts->split_tail >= 2 && kind != kFitset)
+      return fail(GNA_E_INVAL, "opts.split_tail = %d needs a fitset plan", opts->split_tail);
   }
   for (int i = 0; i < n_probs; ++i) {
     rc = validate_problem(problems + i, i);
@@ -660,7 +666,8 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
     if (opts->chunks) sh.C = opts->chunks;
     sh.persistent = opts->persistent;
     if (opts->smear_mfma >= 1) sh.mfma = opts->smear_mfma;
-    if (opts->split_tail) sh.split = opts->split_tail == 2;
+    if (opts->split_tail) sh.split = opts->split_tail - 1;  // 1, 2, 3 -> fused, split, queued
+    if (sh.split == 2) sh.persistent = 1;
   }
   if (kind == kChain && (!opts || opts->smear_mfma == -1) && scan_supported(p) &&
       n_points >= 64)
@@ -747,7 +754,8 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
                        (uint32_t*)(w + off), n, 0u);
     return check_hip(hipGetLastError(), "fill_u32_kernel");
   };
-  if ((rc = zero(L.counters, std::max(p->n_points, 1)))) return rc;
+  if ((rc = zero(L.counters, (int64_t)(p->kind == kFitset ? 2 : 1) * std::max(p->n_points, 1))))
+    return rc;
   if ((rc = zero(L.queue, 4))) return rc;
   if ((rc = zero(L.status, 4))) return rc;
   if (p->kind == kChain && scan_supported(p) && (rc = build_scan_tables(p, s))) return rc;
@@ -877,6 +885,9 @@ extern "C" int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_sta
                        (uint32_t*)(plan->ws + plan->lay.status), (int64_t)4, 0u);
     rc = check_hip(hipStreamSynchronize(s), "clearing the status word");
     if (rc) return rc;
+    if (word & kSpinTimeout)
+      return fail(GNA_E_HIP, "device status word 0x%x: a queued tail gave up waiting for its "
+                  "fit's point tiles (results invalid; rebuild the plan)", word);
     return fail(GNA_E_DOMAIN, "device status word 0x%x (%s%s)", word,
                 (word & kBadMixing) ? "mixing parameter outside [0,1] " : "",
                 (word & kBadPrediction) ? "prediction <= 0 or not finite" : "");

@@ -60,7 +60,11 @@ def test_fitset_fp64_parity(small_set):
     assert fs.status() == 0
 
 
-@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
+TAILS = [1, 2, 3]
+TAIL_IDS = ["fused_tail", "split_tail", "queued_tail"]
+
+
+@pytest.mark.parametrize("tail", TAILS, ids=TAIL_IDS)
 @pytest.mark.parametrize("opts", [
     dict(threads=64, lanes_per_bin=1, chunks=1),
     dict(threads=128, lanes_per_bin=2, chunks=3, persistent=1),
@@ -94,7 +98,7 @@ def test_fitset_split_tail_wide_band(prec):
     tc, tg, tp = ((FP64_RTOL, FP64_RTOL, FP64_RTOL) if prec == "fp64" else
                   (MIXED_CHI2_RTOL, MIXED_GRAD_TOL, MIXED_PRED_RTOL))
     outs = []
-    for tail in (1, 2):
+    for tail in (1, 2, 3):
         fs, got = _run(problems, params, prec=prec, pred=True, split_tail=tail)
         assert fs.shape()["split_tail"] == tail - 1
         assert np.max(rel_err(got["chi2"], chi2)) <= tc
@@ -104,6 +108,7 @@ def test_fitset_split_tail_wide_band(prec):
     # The tails round differently (the split tail scales by norm after the
     # smearing, in FP64); in mixed precision each is within tp of the oracle.
     assert np.max(rel_err(outs[1], outs[0])) <= (1e-13 if prec == "fp64" else 2 * tp)
+    assert np.array_equal(outs[2], outs[1])  # the queued tail is the split tail's arithmetic
 
 
 def test_fitset_mixed(small_set):
@@ -147,7 +152,7 @@ def test_fitset_full_size_sampled():
         assert np.max(grad_error(got["grad"][idx], grad, params[idx], chi2)) <= tg
 
 
-@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
+@pytest.mark.parametrize("tail", TAILS, ids=TAIL_IDS)
 def test_fitset_without_gradient_and_domain_errors(small_set, tail):
     """chi2 and pred without the gradient pass; a fit with s12 outside [0, 1]
     gets NaN and latches the status word, the others are unaffected; a fit
@@ -181,7 +186,7 @@ def test_fitset_without_gradient_and_domain_errors(small_set, tail):
         fs.status()
 
 
-@pytest.mark.parametrize("tail", [1, 2], ids=["fused_tail", "split_tail"])
+@pytest.mark.parametrize("tail", TAILS, ids=TAIL_IDS)
 @pytest.mark.parametrize("nb", [1, 63, 64, 65])
 def test_fitset_single_fit_edge_sizes(tail, nb):
     """One fit of 1, 63, 64 or 65 bins (one slice, a full slice, a ragged
@@ -192,3 +197,29 @@ def test_fitset_single_fit_edge_sizes(tail, nb):
     chi2, grad = oracle.fitset(problems, MODEL, params, n_threads=1)
     assert np.max(rel_err(got["chi2"], chi2)) <= FP64_RTOL
     assert np.max(grad_error(got["grad"], grad, params, chi2)) <= FP64_RTOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_fitset_queued_tail_equals_split_tail(prec):
+    """The queued tail (one persistent launch) gives the split tail's bits for
+    chi^2, gradient and prediction on the 1024-fit batch, on every one of
+    several evaluations in a row (its counters reset themselves), with and
+    without the gradient."""
+    import paper_1804_07682_amd as gna
+    problems, params = W.config4()
+    problems = _with_data(problems)
+    P = torch.tensor(params, device=DEV)
+    ref = gna.FitSet(problems, MODEL, prec=prec, opts={"split_tail": 2}, device=DEV)
+    q = gna.FitSet(problems, MODEL, prec=prec, opts={"split_tail": 3}, device=DEV)
+    assert q.shape()["split_tail"] == 2 and q.shape()["persistent"] == 1
+    a = {k: v.cpu().numpy() for k, v in ref.eval(P, grad=True, pred=True).items()}
+    for rep in range(3):
+        b = {k: v.cpu().numpy() for k, v in q.eval(P, grad=True, pred=True).items()}
+        for k in ("chi2", "grad", "pred"):
+            assert np.array_equal(b[k], a[k]), (rep, k)
+    c = q.eval(P, grad=False)["chi2"].cpu().numpy()
+    assert np.array_equal(c, ref.eval(P, grad=False)["chi2"].cpu().numpy())
+    assert q.status() == 0
+    # a changed parameter set after the repeated ones
+    P2 = P * 1.01
+    assert np.array_equal(q.eval(P2)["chi2"].cpu().numpy(), ref.eval(P2)["chi2"].cpu().numpy())

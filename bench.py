@@ -142,6 +142,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the automatic launch shape (no autotuning), for counter runs")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--opts", default=None,
+                    help="with --only fitset*: launch options as JSON, e.g. "
+                         "'{\"split_tail\": 2, \"threads\": 128}' (no autotuning)")
     return ap.parse_args()
 
 
@@ -630,8 +633,10 @@ def main():
         elif o in ("fitset", "fitset1", "fitsetq"):
             opts = {"fitset1": {"split_tail": 1, "persistent": 1},
                     "fitsetq": {"split_tail": 3, "persistent": 1}}.get(o)
+            if args.opts:
+                opts = dict(opts or {}, **json.loads(args.opts))
             r = bench_fitset(gna, W, torch, timer, dev, args.steps, args.prec, opts=opts,
-                             tune=o == "fitset")
+                             tune=o == "fitset" and not args.opts)
             for k in ("problems", "P", "plan"):
                 r.pop(k)
             log(f"{o}: {r}")
@@ -758,16 +763,15 @@ def main():
             r.pop("plan").close()
             fs[p] = r
             for tag, sp in (("one_launch_queued_tail", 3), ("one_launch_fused_tail", 1)):
-                f1 = bench_fitset(gna, W, torch, timer, dev, 50, p,
-                                  opts={"split_tail": sp, "persistent": 1}, tune=False)
+                f1 = bench_fitset(gna, W, torch, timer, dev, 50, p, opts={"split_tail": sp})
                 f1.pop("problems"), f1.pop("P"), f1.pop("plan").close()
                 fs[p][tag] = f1
         fs["mixed_vs_fp64"] = fitset_errors(gna, W, torch, dev, problems, P4)
         fs["note"] = ("the autotuned shape (split_tail 1: the point pass plus two tail "
-                      "launches; 2: the queued tail in one persistent launch), and two "
-                      "one-launch shapes with the automatic lane counts: the queued tail "
-                      "(tail slices as queue items after the point tiles) and the fused "
-                      "tail (each fit's tail in the work-group of its last tile)")
+                      "launches; 2: the queued tail in one persistent launch), and the "
+                      "autotuned one-launch forms: the queued tail (one tail item per fit "
+                      "in the persistent queue, after the fit's tiles) and the fused tail "
+                      "(each fit's tail in the work-group of its last tile)")
         line["fitset"] = fs
         log("table-1 analogue (GPU side) ...")
         t1_gpu = table1_gpu(gna, W, torch, timer, dev)

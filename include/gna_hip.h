@@ -262,10 +262,12 @@ typedef struct gna_problem {
  *                  stores bin sums, and two more launches run the tails of
  *                  all fits with one wavefront per 64-row slice, then add
  *                  each fit's partials in a fixed order; 3: queued tail,
- *                  the same tail work as queue items after the point tiles
- *                  of one persistent launch (a slice waits for its own fit's
- *                  tiles; implies persistent = 1; same results as 2, bit for
- *                  bit).
+ *                  one launch: the persistent queue holds the point tiles
+ *                  and, some way after each fit's last tile, that fit's
+ *                  tail (one work-group waits for the fit's tiles, then runs
+ *                  its slices and the fixed-order sum; implies
+ *                  persistent = 1; same results as 2, bit for bit).  A
+ *                  nonzero value also keeps gna_plan_autotune to that tail.
  */
 typedef struct gna_launch_opts {
   int32_t threads;

@@ -705,58 +705,47 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_final_kernel(TailArgs
 }
 
 // ---- queued tail (uneven batches, one persistent launch) --------------------
-// The queue holds the point tiles (longest first), then the tail work of
-// tail_fwd as items of one slice per wavefront, longest slices first.  A
-// wavefront that takes a slice of fit f waits until f's point tiles have all
-// counted themselves done: every tile index was handed out before any tail
-// index, and the work-groups holding tiles wait on nothing, so the wait ends
-// (it is bounded all the same: past kSpinLimit sleeps the wavefront gives up
-// and latches kSpinTimeout).  The wavefront that finishes a fit's last slice
-// adds the fit's slice partials as tail_final does and clears the fit's two
-// counters for the next evaluation.  Same operations in the same order as the
-// split tail, so the results are the same bits.
+// The queue (built by the plan) interleaves the point tiles with one tail item
+// per fit, each after all of its fit's tiles.  The work-group that takes fit
+// f's tail waits until f's tiles have counted themselves done: each of them
+// was handed out before, to a work-group that waits on nothing, so the wait
+// ends (it is bounded all the same: past kSpinLimit sleeps the work-group
+// latches kSpinTimeout and waits no more in this launch).  One agent-scope
+// acquire then covers every bin sum of the fit; its wavefronts take the fit's
+// 64-row slices in
+// turn (the slice work of tail_fwd), and wavefront 0 adds the slice partials
+// as tail_final does, after a work-group barrier.  The fit's data crosses
+// work-groups once per fit, not once per slice (each crossing costs an L2
+// write-back or invalidation on a GPU of several L2s).  Same operations in
+// the same order as the split tail, so the results are the same bits.
 constexpr uint32_t kSpinLimit = 1u << 20;  // >= 1M sleeps of 128 clocks: tens of ms at least
 
 template <class R, bool GRAD>
-__device__ void queued_slice(const ChainArgs<R>& a, int64_t idx, int lane, R* win) {
-  const int64_t item = a.order[idx];
-  const int f = a.slice_prob[item];
-  const uint32_t need = (uint32_t)(a.probs[f].n_bin_blocks * a.probs[f].C);
-  uint32_t late = 0;
-  if (lane == 0) {
-    for (uint32_t spin = 0;; ++spin) {
-      if (__hip_atomic_load(&a.counters[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)
-        break;
-      if (spin >= kSpinLimit) {
-        late = 1;
+__device__ void queued_fit(const ChainArgs<R>& a, int f, int wave, int nw, int lane, R* win,
+                           uint32_t* late) {
+  if (threadIdx.x == 0) {
+    const uint32_t need = (uint32_t)(a.probs[f].n_bin_blocks * a.probs[f].C);
+    uint32_t spin = 0;
+    while (!*late &&
+           __hip_atomic_load(&a.counters[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (++spin > kSpinLimit) {
+        *late = 1u;
+        __hip_atomic_fetch_or(a.status, (uint32_t)kSpinTimeout, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
     }
-  }
-  late = __shfl(late, 0, kWave);
-  if (late)
-    __hip_atomic_fetch_or(a.status, (uint32_t)kSpinTimeout, __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the fit's bin sums
-  slice_tail<R, GRAD>(a, item, lane, win);
-  uint32_t last = 0;
-  if (lane == 0) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the partials, before the count
-    const uint32_t prev = __hip_atomic_fetch_add(&a.slice_done[f], 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev + 1 == (uint32_t)a.probs[f].n_slices) ? 1u : 0u;
-  }
-  last = __shfl(last, 0, kWave);
-  if (!last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other slices' partials
-  fit_final<R, GRAD>(a, f, lane);
-  // Every wavefront of this fit has passed its wait and counted its slice:
-  // the fit's counters start the next evaluation at zero.
-  if (lane == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the fit's bin sums
+    // Every tile of the fit has counted: the counter starts the next
+    // evaluation at zero (the launch boundary publishes the store).
     a.counters[f] = 0u;
-    a.slice_done[f] = 0u;
   }
+  __syncthreads();
+  const ProbDev pd = a.probs[f];
+  for (int s = wave; s < pd.n_slices; s += nw) slice_tail<R, GRAD>(a, pd.slice_off + s, lane, win);
+  __syncthreads();  // the slice partials of every wavefront
+  if (wave == 0) fit_final<R, GRAD>(a, f, lane);
 }
 
 // Window LDS of one wavefront of the queued tail.
@@ -778,25 +767,25 @@ __global__ void __launch_bounds__(1024) chain_queued_kernel(ChainArgs<R> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ BaseLds bl;
   __shared__ uint32_t next;
+  __shared__ uint32_t late;  // set when a wait gave up (the rest of the launch does not wait)
   const int nw = blockDim.x / kWave;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x - (threadIdx.x / kWave) * kWave;
   TileLds L{lds_raw, (int)blockDim.x, 0, 1};
-  const int64_t n_tail = (a.n_slices + nw - 1) / nw;
+  if (threadIdx.x == 0) late = 0u;
   for (;;) {
     if (threadIdx.x == 0)
       next = __hip_atomic_fetch_add(&a.queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const int64_t t = next;
     __syncthreads();
-    if (t >= a.n_tiles + n_tail) break;
-    if (t < a.n_tiles) {
-      process_tile<R, GRAD, true, true>(a, t, L, bl);
-    } else {
-      const int64_t idx = (t - a.n_tiles) * nw + wave;
-      if (idx < a.n_slices)
-        queued_slice<R, GRAD>(a, idx, lane,
-                              reinterpret_cast<R*>(lds_raw) + (size_t)wave * kQueuedWin<R, GRAD>);
-    }
+    if (t >= a.n_items) break;
+    const int32_t e = a.q_items[t];
+    if (e >= 0)
+      process_tile<R, GRAD, true, true>(a, e, L, bl);
+    else
+      queued_fit<R, GRAD>(a, -1 - e, wave, nw, lane,
+                          reinterpret_cast<R*>(lds_raw) + (size_t)wave * kQueuedWin<R, GRAD>,
+                          &late);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -876,6 +865,13 @@ int launch_queued(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   gna_plan::LaunchCache& lc = p->launch_cache[GRAD];
   if (!lc.ready) {
     lc.lds = queued_lds_bytes(p, sh);
+    if (lc.lds > 64 * 1024) {
+      const int rc = check_hip(hipFuncSetAttribute((const void*)kern,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lc.lds),
+                               "hipFuncSetAttribute (queued-tail LDS)");
+      if (rc) return rc;
+    }
     lc.occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&lc.occ, kern, sh.threads, lc.lds) !=
             hipSuccess ||
@@ -885,9 +881,7 @@ int launch_queued(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
     lc.rlds = 0;
     lc.ready = 1;
   }
-  const int64_t grid = std::min<int64_t>(a.n_tiles + (a.n_slices + sh.threads / kWave - 1) /
-                                                         (sh.threads / kWave),
-                                         (int64_t)lc.occ * p->cu_count);
+  const int64_t grid = std::min<int64_t>(a.n_items, (int64_t)lc.occ * p->cu_count);
   if (grid < 1) return GNA_OK;
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.threads), lc.lds, s, a);
   return check_hip(hipGetLastError(), "chain_queued_kernel launch");
@@ -929,11 +923,10 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
   a.pred = pred;
   const bool pers = p->shape.persistent != 0;
   if (p->shape.split == 2) {
+    a.q_items = (const int32_t*)(w + L.q_items);
+    a.n_items = p->n_qitems;
     a.slice_prob = (const int32_t*)(w + L.slice_prob);
-    a.order = (const int32_t*)(w + L.fwd_order);
-    a.n_slices = p->total_slices;
     a.part = (double*)(w + L.tailpart);
-    a.slice_done = (uint32_t*)(w + L.counters) + p->n_points;
     return grad ? launch_queued<R, true>(p, a, s) : launch_queued<R, false>(p, a, s);
   }
   if (p->shape.split) {

@@ -21,6 +21,10 @@ constexpr int kSlice = 64;          // rows per smearing-band slice (one wavefro
 constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kGLTable = kMaxOrder * (kMaxOrder + 1) / 2;  // rules of order 1..64
 constexpr double kBandZ = 6.0;      // erf(z) == +-1 in FP64 beyond |z| = 5.93
+// Queued tail: a fit's tail item sits at least this many wavefronts per CU
+// of queue entries after its last tile (with the CU count and the
+// work-group size: about one turnover of the resident work-groups).
+constexpr int kQueuedLagWaves = 16;
 
 // ---- device-side descriptors (live in the workspace) -----------------------
 struct ProbDev {
@@ -83,14 +87,14 @@ struct ChainArgs {
   double* chi2;
   double* grad;
   double* pred;
-  // Queued tail (uneven batches, one launch): the fit of each slice, the
-  // slices in queue order, the per-slice partial sums and the per-fit count
-  // of finished slices (counters holds the per-fit count of finished tiles).
+  // Queued tail (uneven batches, one launch): the queue (entry >= 0: a tile
+  // index; < 0: the tail of fit -1 - entry), the fit of each slice and the
+  // per-slice partial sums (counters holds the per-fit count of finished
+  // tiles).
+  const int32_t* q_items;
+  int64_t n_items;
   const int32_t* slice_prob;
-  const int32_t* order;
-  int64_t n_slices;
   double* part;
-  uint32_t* slice_done;
 };
 
 // kSpinTimeout: a queued tail waited longer than its bound for a fit's point
@@ -103,7 +107,7 @@ enum PlanKind { kChain = 0, kFitset = 1 };
 struct Layout {
   size_t probs = 0, slices = 0, slice_prob = 0, tiles = 0, E = 0, f = 0, L = 0, wL = 0,
          edges = 0, data = 0, gl = 0, Rv = 0, scratch = 0, counters = 0, queue = 0, status = 0,
-         Rdense = 0, tailpart = 0, fwd_order = 0, total = 0;
+         Rdense = 0, tailpart = 0, fwd_order = 0, q_items = 0, total = 0;
 };
 
 struct Shape {
@@ -111,8 +115,9 @@ struct Shape {
   int share = 1;  // MFMA kernel: tiles with common dm2 share their phases (if the plan allows)
   // Uneven batch: 0 = each fit's tail in the work-group that finishes its
   // last tile; 1 = the tails in two more launches, wide over the GPU;
-  // 2 = queued tail: the same wide tail work as queue items after the point
-  // tiles, in the one persistent launch.
+  // 2 = queued tail: one tail item per fit in the one persistent launch's
+  // queue, interleaved with the point tiles (a fit's tail some way after its
+  // last tile).
   int split = 0;
 };
 
@@ -133,6 +138,8 @@ struct gna_plan {
   int64_t scratch_elems;
   gna::Shape shape;
   int64_t n_tiles;        // fitset: tiles in the queue; chain: tiles per point
+  int64_t n_qitems;       // queued tail: queue entries (tiles and fit tails)
+  int tail_pin;           // fitset: opts.split_tail (nonzero: the autotuner keeps that tail)
   int cu_count;
   size_t lds_limit;       // LDS budget of the generic kernel (64 KB)
   size_t lds_device;      // LDS per work-group the device allows (160 KB on gfx950)
@@ -192,6 +199,9 @@ struct ChainLds {
 };
 ChainLds chain_lds(const gna_plan* p, const Shape& sh);
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh);
+// LDS a shape may use: 64 KB for the generic kernel, the device's limit for
+// the queued-tail kernel.
+size_t shape_lds_limit(const gna_plan* p, const Shape& sh);
 // Dynamic LDS of the queued-tail kernel: one staging window per wavefront.
 size_t queued_lds_bytes(const gna_plan* p, const Shape& sh);
 // Sets the per-problem tiling of `sh` (and, for a fitset, rebuilds and

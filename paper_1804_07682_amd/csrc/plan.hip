@@ -6,6 +6,7 @@
 // that build the Gauss-Legendre rules, the quadrature energies E_k, the
 // flux factors f_k = n0 w_k S(E_k) sigma(E_k) and the banded smearing matrix.
 #include <algorithm>
+#include <deque>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -304,6 +305,12 @@ ChainLds chain_lds(const gna_plan* p, const Shape& sh) {
   return c;
 }
 
+size_t shape_lds_limit(const gna_plan* p, const Shape& sh) {
+  // The queued-tail kernel asks for its LDS at launch (up to the device's
+  // per-work-group limit); the generic kernel stays within 64 KB.
+  return sh.split == 2 ? p->lds_device : p->lds_limit;
+}
+
 size_t chain_lds_bytes(const gna_plan* p, const Shape& sh) {
   if (sh.split == 1) return 0;  // the point pass alone keeps nothing in LDS
   if (sh.split == 2) return queued_lds_bytes(p, sh);  // the tail items' windows
@@ -378,7 +385,8 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
             sh.persistent = pers;
             sh.mfma = 0;
             sh.split = split;
-            if (chain_lds_bytes(p, sh) > p->lds_limit) continue;
+            if (p->tail_pin && split != p->tail_pin - 1) continue;  // the caller chose the tail
+            if (chain_lds_bytes(p, sh) > shape_lds_limit(p, sh)) continue;
             out.push_back(sh);
           }
       }
@@ -395,6 +403,66 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
   return out;
 }
 
+// Queue of the queued tail: the point tiles with one tail item per fit.  The
+// fits go in order of falling tail work (the band diagonals of their slices),
+// each fit's tiles longest first; a fit's tail item is placed once about one
+// turnover of the resident work-groups (kQueuedLagWaves wavefronts per CU) of
+// entries has followed its last tile, ahead of later tiles.  So a tail's wait
+// for its fit's tiles is short, the tails' band reads overlap the arithmetic
+// of later tiles, the longest tails start early, and every tile a tail waits
+// for was handed out before it, to a work-group that waits on nothing.
+template <class TileAt>
+int queued_order(const gna_plan* p, const Shape& sh, size_t n_items, TileAt tile_at,
+                 std::vector<TileDev>& tiles, std::vector<int32_t>& qitems) {
+  const int nf = (int)p->probs.size();
+  const int nw = sh.threads / kWave;
+  std::vector<std::vector<size_t>> of_fit(nf);
+  for (size_t k = 0; k < n_items; ++k) of_fit[tile_at(k).point].push_back(k);  // longest first
+  std::vector<double> tail(nf, 0.0);
+  for (size_t i = 0; i < p->slices.size(); ++i) tail[p->slice_prob_host[i]] += p->slices[i].nd;
+  std::vector<int> fits(nf);
+  for (int f = 0; f < nf; ++f) fits[f] = f;
+  std::stable_sort(fits.begin(), fits.end(), [&](int a, int b) { return tail[a] > tail[b]; });
+  const int64_t lag = std::max<int64_t>(1, (int64_t)kQueuedLagWaves * p->cu_count / nw);
+  std::deque<std::pair<int, int64_t>> ready;  // (fit, first queue position allowed)
+  auto emit_ready = [&](bool all) {
+    while (!ready.empty() && (all || ready.front().second <= (int64_t)qitems.size())) {
+      qitems.push_back(-1 - ready.front().first);
+      ready.pop_front();
+    }
+  };
+  for (int f : fits) {
+    for (size_t k : of_fit[f]) {
+      emit_ready(false);
+      qitems.push_back((int32_t)tiles.size());
+      tiles.push_back(tile_at(k));
+    }
+    ready.emplace_back(f, (int64_t)qitems.size() + lag);
+  }
+  emit_ready(true);
+  // A tail's wait ends only if all of its fit's tiles sit earlier in the
+  // queue: check that, and that each tile and each fit's tail appears once.
+  std::vector<size_t> tiles_seen(nf, 0);
+  std::vector<char> tail_seen(nf, 0);
+  int64_t n_t = 0, n_f = 0;
+  for (int32_t e : qitems) {
+    if (e >= 0) {
+      if (e != n_t++) return fail(GNA_E_INVAL, "queued tail: tile %d out of order", e);
+      ++tiles_seen[tiles[e].point];
+      continue;
+    }
+    const int f = -1 - e;
+    if (f >= nf || tail_seen[f] || tiles_seen[f] != of_fit[f].size())
+      return fail(GNA_E_INVAL, "queued tail: fit %d queued twice or before its tiles", f);
+    tail_seen[f] = 1;
+    ++n_f;
+  }
+  if (n_t != (int64_t)n_items || n_f != nf)
+    return fail(GNA_E_INVAL, "queued tail: %lld tiles, %lld fits queued", (long long)n_t,
+                (long long)n_f);
+  return GNA_OK;
+}
+
 int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
   if (sh.threads < kWave || sh.threads > 1024 || (sh.threads & (sh.threads - 1)))
     return fail(GNA_E_INVAL, "threads = %d invalid", sh.threads);
@@ -407,10 +475,11 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
     return fail(GNA_E_UNSUPPORTED, "a queued tail needs the persistent launch");
   if (sh.mfma && !(p->kind == kChain && scan_supported(p)))
     return fail(GNA_E_UNSUPPORTED, "MFMA smearing needs a chain plan with n_bins <= 256");
-  if (!sh.mfma && chain_lds_bytes(p, sh) > p->lds_limit)
+  if (!sh.mfma && chain_lds_bytes(p, sh) > shape_lds_limit(p, sh))
     return fail(GNA_E_UNSUPPORTED, "shape needs %zu bytes of LDS (limit %zu)",
-                chain_lds_bytes(p, sh), p->lds_limit);
+                chain_lds_bytes(p, sh), shape_lds_limit(p, sh));
   std::vector<TileDev> tiles;
+  std::vector<int32_t> qitems;
   for (size_t i = 0; i < p->probs.size(); ++i) {
     ProbDev& pd = p->probs[i];
     pd.G = sh.G;
@@ -454,9 +523,16 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
     // Longest-processing-time order: the queue hands out the costliest tiles first.
     std::stable_sort(items.begin(), items.end(),
                      [](const Item& a, const Item& b) { return a.cost > b.cost; });
-    for (auto& it : items) tiles.push_back(it.t);
+    if (sh.split != 2) {
+      for (auto& it : items) tiles.push_back(it.t);
+    } else {
+      const int rc =
+          queued_order(p, sh, items.size(), [&](size_t k) { return items[k].t; }, tiles, qitems);
+      if (rc) return rc;
+    }
     p->n_tiles = (int64_t)tiles.size();
   }
+  p->n_qitems = (int64_t)qitems.size();
   p->shape = sh;
   p->share_phases = p->share_allowed && sh.share;
   p->launch_cache[0].ready = p->launch_cache[1].ready = 0;
@@ -469,6 +545,12 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
       rc = check_hip(hipMemcpyAsync(p->ws + p->lay.tiles, tiles.data(),
                                     sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice, s),
                      "hipMemcpyAsync (tile list)");
+      if (rc) return rc;
+    }
+    if (!qitems.empty()) {
+      rc = check_hip(hipMemcpyAsync(p->ws + p->lay.q_items, qitems.data(), 4 * qitems.size(),
+                                    hipMemcpyHostToDevice, s),
+                     "hipMemcpyAsync (queue)");
       if (rc) return rc;
     }
     // The host vectors die here: finish the copies first.
@@ -511,14 +593,15 @@ void compute_layout(gna_plan* p, PlanBuild& b) {
   L.gl = take(16 * kGLTable);
   L.Rv = take(rs * p->total_band);
   L.scratch = take(rs * p->scratch_elems);
-  // Chain: one completion counter per point.  Fitset: per fit, the finished
-  // tiles, then (queued tail) the finished slices.
-  L.counters = take(4 * (size_t)(p->kind == kFitset ? 2 : 1) * std::max(p->n_points, 1));
+  // One completion counter per point (fitset: per fit).
+  L.counters = take(4 * (size_t)std::max(p->n_points, 1));
   L.queue = take(16);
   L.status = take(16);
   L.Rdense = take(p->kind == kChain ? scan_dense_bytes(p) : 0);
   L.tailpart = take(p->kind == kFitset ? 6 * 8 * p->total_slices : 0);
   L.fwd_order = take(4 * p->fwd_order.size());
+  // Queued tail: one entry per tile and per fit.
+  L.q_items = take(p->kind == kFitset ? 4 * ((size_t)p->tile_capacity + p->n_probs) : 0);
   L.total = off;
 }
 
@@ -667,6 +750,7 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
     sh.persistent = opts->persistent;
     if (opts->smear_mfma >= 1) sh.mfma = opts->smear_mfma;
     if (opts->split_tail) sh.split = opts->split_tail - 1;  // 1, 2, 3 -> fused, split, queued
+    p->tail_pin = opts->split_tail;
     if (sh.split == 2) sh.persistent = 1;
   }
   if (kind == kChain && (!opts || opts->smear_mfma == -1) && scan_supported(p) &&
@@ -754,8 +838,7 @@ int upload_and_build(PlanBuild& b, void* ws, size_t ws_bytes, hipStream_t s) {
                        (uint32_t*)(w + off), n, 0u);
     return check_hip(hipGetLastError(), "fill_u32_kernel");
   };
-  if ((rc = zero(L.counters, (int64_t)(p->kind == kFitset ? 2 : 1) * std::max(p->n_points, 1))))
-    return rc;
+  if ((rc = zero(L.counters, std::max(p->n_points, 1)))) return rc;
   if ((rc = zero(L.queue, 4))) return rc;
   if ((rc = zero(L.status, 4))) return rc;
   if (p->kind == kChain && scan_supported(p) && (rc = build_scan_tables(p, s))) return rc;

@@ -223,3 +223,27 @@ def test_fitset_queued_tail_equals_split_tail(prec):
     # a changed parameter set after the repeated ones
     P2 = P * 1.01
     assert np.array_equal(q.eval(P2)["chi2"].cpu().numpy(), ref.eval(P2)["chi2"].cpu().numpy())
+
+
+def test_fitset_autotune_keeps_the_chosen_tail(small_set):
+    """With split_tail set, the autotuner times only shapes of that tail: the
+    queued tail stays one persistent launch, and keeps the bits of the split
+    tail of the same tiling (lane and chunk counts fix the order of the bin
+    sums)."""
+    import paper_1804_07682_amd as gna
+    problems, params = small_set
+    P = torch.tensor(params, device=DEV)
+    ref = gna.FitSet(problems, MODEL, prec="fp64", opts={"split_tail": 2}, device=DEV)
+    a = ref.eval(P)["chi2"].cpu().numpy()
+    for tail in (3, 2, 1):
+        fs = gna.FitSet(problems, MODEL, prec="fp64", opts={"split_tail": tail}, device=DEV)
+        shape = fs.autotune(P, reps=2)
+        assert shape["split_tail"] == tail - 1
+        got = fs.eval(P)["chi2"].cpu().numpy()
+        assert np.max(rel_err(got, a)) <= 1e-13
+        if tail == 3:
+            assert shape["persistent"] == 1
+            same = {k: shape[k] for k in ("threads", "lanes_per_bin", "chunks")}
+            twin = gna.FitSet(problems, MODEL, prec="fp64", opts=dict(same, split_tail=2),
+                              device=DEV)
+            assert np.array_equal(got, twin.eval(P)["chi2"].cpu().numpy())

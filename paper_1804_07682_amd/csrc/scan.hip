@@ -55,6 +55,38 @@ struct Acc<double> {
   __device__ static int row(int krow, int v) { return krow + 4 * v; }
 };
 
+// acc += sum over column blocks lo <= kb <= hi of A(kb) B(kb), with the A
+// operands of one row tile read from global memory in MFMA operand order
+// (At: the tile's first block, lane offset included; block kb at
+// At + kb * 256) and B from the LDS operand bb.  The A loads of up to
+// kGemmBatch blocks go out together before their MFMAs, so a row tile waits
+// for memory once per batch, not once per block.  Same MFMAs in the same
+// order as one block at a time.
+constexpr int kGemmBatch = 6;
+template <class R, class A4>
+__device__ __forceinline__ void gemm_row_global(const R* __restrict__ At, int lo, int hi,
+                                                const R* bb, int krow, int n, A4& acc) {
+  for (int kb0 = lo; kb0 <= hi; kb0 += kGemmBatch) {
+    R av[kGemmBatch][4];
+#pragma unroll
+    for (int b = 0; b < kGemmBatch; ++b)
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+        av[b][st] = (kb0 + b <= hi) ? At[((kb0 + b) * 4 + st) * 64] : R(0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int b = 0; b < kGemmBatch; ++b) {
+      if (kb0 + b > hi) break;
+      const int kb = kb0 + b;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+        acc = Acc<R>::mfma(av[b][st], bv, acc);
+      }
+    }
+  }
+}
+
 template <class R>
 struct ScanArgs {
   int32_t B, nb, mt, ppb, nL, nq;
@@ -413,15 +445,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             }
           }
         } else {
-          const R* At = a.RA + ((int64_t)I * mt) * 256 + lane;
-          for (int kb = lo; kb <= hi; ++kb) {
-#pragma unroll
-            for (int st = 0; st < 4; ++st) {
-              const R av = At[(kb * 4 + st) * 64];
-              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-              acc[u] = Acc<R>::mfma(av, bv, acc[u]);
-            }
-          }
+          gemm_row_global<R>(a.RA + ((int64_t)I * mt) * 256 + lane, lo, hi, bb, krow, n, acc[u]);
         }
       }
     }
@@ -573,15 +597,8 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
                 }
               }
             } else {
-              const R* At = a.RT + ((int64_t)J * mt) * 256 + lane;
-              for (int kb = lo; kb <= hi; ++kb) {
-#pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                  const R av = At[(kb * 4 + st) * 64];
-                  const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
-                  acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
-                }
-              }
+              gemm_row_global<R>(a.RT + ((int64_t)J * mt) * 256 + lane, lo, hi, bb, krow, n,
+                                 acc2[u]);
             }
           }
         }

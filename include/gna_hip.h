@@ -385,6 +385,16 @@ int gna_plan_rebuild(gna_plan* plan, void* stream);
 int gna_debug_inject_hip_errors(int32_t count);
 /* Injected failures not yet consumed. */
 int32_t gna_debug_pending_hip_errors(void);
+/* The bounded wait of the queued tail (fitset plans, split_tail = 3): from
+ * the next evaluation on, a tail waits for `extra_tiles` tiles more than its
+ * fit has (so with extra_tiles > 0 no wait can end by the count) and gives
+ * up after `spin_limit` sleeps (0: the default bound, about 2^20).  A wait
+ * that gives up latches a status bit that gna_plan_status reports as
+ * GNA_E_HIP; the launch still ends normally, its results are not valid, and
+ * gna_plan_rebuild restores the plan.  gna_debug_queued_wait(plan, 0, 0)
+ * restores the defaults.  Errors: GNA_E_INVAL (NULL or not a fitset plan,
+ * negative values). */
+int gna_debug_queued_wait(gna_plan* plan, int32_t spin_limit, int32_t extra_tiles);
 
 /* ---- unfused transformations (vector in / vector out) -------------------- */
 /*

@@ -139,6 +139,7 @@ SIGNATURES = {
     "gna_plan_rebuild": (C.c_int, [_PlanP, _vp]),
     "gna_debug_inject_hip_errors": (C.c_int, [C.c_int32]),
     "gna_debug_pending_hip_errors": (C.c_int32, []),
+    "gna_debug_queued_wait": (C.c_int, [_PlanP, C.c_int32, C.c_int32]),
 }
 
 _lib = None

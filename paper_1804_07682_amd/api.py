@@ -541,6 +541,13 @@ class FitSet(_PlanBase):
             res["pred"] = pr
         return res
 
+    def debug_queued_wait(self, spin_limit=0, extra_tiles=0):
+        """Bound of the queued tail's wait, for tests of its failure path: each
+        tail waits for `extra_tiles` tiles beyond its fit's and gives up after
+        `spin_limit` sleeps (0: the default).  (0, 0) restores the defaults."""
+        check(load().gna_debug_queued_wait(self._plan, int(spin_limit), int(extra_tiles)),
+              "gna_debug_queued_wait")
+
 
 class Chi2Fn(torch.autograd.Function):
     """chi^2 of a chain plan as a differentiable function of params [B, 5].

@@ -724,11 +724,11 @@ template <class R, bool GRAD>
 __device__ void queued_fit(const ChainArgs<R>& a, int f, int wave, int nw, int lane, R* win,
                            uint32_t* late) {
   if (threadIdx.x == 0) {
-    const uint32_t need = (uint32_t)(a.probs[f].n_bin_blocks * a.probs[f].C);
+    const uint32_t need = (uint32_t)(a.probs[f].n_bin_blocks * a.probs[f].C) + a.need_extra;
     uint32_t spin = 0;
     while (!*late &&
            __hip_atomic_load(&a.counters[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-      if (++spin > kSpinLimit) {
+      if (++spin > a.spin_limit) {
         *late = 1u;
         __hip_atomic_fetch_or(a.status, (uint32_t)kSpinTimeout, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
@@ -927,6 +927,8 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
     a.n_items = p->n_qitems;
     a.slice_prob = (const int32_t*)(w + L.slice_prob);
     a.part = (double*)(w + L.tailpart);
+    a.spin_limit = p->q_spin_limit ? p->q_spin_limit : kSpinLimit;
+    a.need_extra = p->q_need_extra;
     return grad ? launch_queued<R, true>(p, a, s) : launch_queued<R, false>(p, a, s);
   }
   if (p->shape.split) {
@@ -953,3 +955,16 @@ int launch_chain(gna_plan* p, const double* params, int32_t B, double* chi2, dou
 }
 
 }  // namespace gna
+
+extern "C" int gna_debug_queued_wait(gna_plan* plan, int32_t spin_limit, int32_t extra_tiles) {
+  gna::clear_error();
+  if (!plan) return gna::fail(GNA_E_INVAL, "plan is NULL");
+  if (plan->kind != gna::kFitset)
+    return gna::fail(GNA_E_INVAL, "gna_debug_queued_wait: not a fitset plan");
+  if (spin_limit < 0 || extra_tiles < 0)
+    return gna::fail(GNA_E_INVAL, "gna_debug_queued_wait: spin_limit %d, extra_tiles %d < 0",
+                     spin_limit, extra_tiles);
+  plan->q_spin_limit = (uint32_t)spin_limit;
+  plan->q_need_extra = (uint32_t)extra_tiles;
+  return GNA_OK;
+}

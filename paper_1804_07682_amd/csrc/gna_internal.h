@@ -95,6 +95,8 @@ struct ChainArgs {
   int64_t n_items;
   const int32_t* slice_prob;
   double* part;
+  uint32_t spin_limit;  // sleeps before a tail's wait gives up
+  uint32_t need_extra;  // tiles a tail waits for beyond its fit's (0; tests of the bound)
 };
 
 // kSpinTimeout: a queued tail waited longer than its bound for a fit's point
@@ -140,6 +142,8 @@ struct gna_plan {
   int64_t n_tiles;        // fitset: tiles in the queue; chain: tiles per point
   int64_t n_qitems;       // queued tail: queue entries (tiles and fit tails)
   int tail_pin;           // fitset: opts.split_tail (nonzero: the autotuner keeps that tail)
+  uint32_t q_spin_limit;  // queued tail: 0 = the default bound (gna_debug_queued_wait)
+  uint32_t q_need_extra;
   int cu_count;
   size_t lds_limit;       // LDS budget of the generic kernel (64 KB)
   size_t lds_device;      // LDS per work-group the device allows (160 KB on gfx950)

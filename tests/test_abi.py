@@ -244,3 +244,4 @@ def test_binding_rejects_short_host_arrays(lib):
     assert L.shape == (1,) and w is None
     with pytest.raises(ValueError, match="theta"):
         api._theta4([7.5e-5, 2.5e-3, 0.3])
+    assert lib.gna_debug_queued_wait(None, 0, 0) == -1  # no plan

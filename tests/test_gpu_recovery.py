@@ -6,7 +6,9 @@ runs and exits normally.
   on the host (the restart point) and then gives the same bits as before;
 * Chain.eval(recover=True) does that by itself;
 * the transformation graph, with failover switched on, computes a failed GPU
-  node on the CPU (counted), and gives the oracle's result.
+  node on the CPU (counted), and gives the oracle's result;
+* the queued tail's bounded wait, made unsatisfiable from the host, ends the
+  launch normally and is reported.
 """
 import numpy as np
 import pytest
@@ -75,6 +77,33 @@ def test_fitset_rebuild_after_injected_failure():
     assert np.array_equal(got["chi2"], ref["chi2"]) and np.array_equal(got["grad"], ref["grad"])
     chi2, _ = oracle.fitset(problems, MODEL, params, n_threads=8)
     assert np.max(rel_err(got["chi2"], chi2)) <= FP64_RTOL
+
+
+def test_queued_tail_wait_bound_is_reported_and_rebuild_recovers():
+    """The queued tail's wait is bounded: made unsatisfiable from the host
+    (each tail waits for one tile more than its fit has, and gives up after
+    64 sleeps), the launch still ends, the status reports the timeout as a
+    HIP error, and a rebuild gives the plan's earlier bits back."""
+    import paper_1804_07682_amd as gna
+    problems, params = W.config4(n_fits=24)
+    problems = [with_data(p, MODEL, W.config4_data_seed(f)) for f, p in enumerate(problems)]
+    fs = gna.FitSet(problems, MODEL, opts={"split_tail": 3}, device=DEV)
+    assert fs.shape()["split_tail"] == 2
+    P = torch.tensor(params, device=DEV)
+    ref = {k: v.cpu().numpy().copy() for k, v in fs.eval(P, grad=True).items()}
+    assert fs.status() == 0
+    fs.debug_queued_wait(spin_limit=64, extra_tiles=1)
+    fs.eval(P, grad=True)
+    with pytest.raises(gna.GnaError, match="queued tail"):
+        fs.status()
+    fs.debug_queued_wait(0, 0)
+    fs.rebuild()
+    for _ in range(2):
+        got = {k: v.cpu().numpy() for k, v in fs.eval(P, grad=True).items()}
+        assert np.array_equal(got["chi2"], ref["chi2"]) and np.array_equal(got["grad"], ref["grad"])
+    assert fs.status() == 0
+    with pytest.raises(gna.GnaError):
+        fs.debug_queued_wait(-1, 0)
 
 
 def test_graph_failover_computes_the_failed_node_on_the_cpu(cfg0):

@@ -340,13 +340,17 @@ int gna_fitset_eval(gna_plan* plan, const double* params_dev, double* chi2_dev,
 /*
  * Synchronizes `stream`, then reads and clears the plan's device status word.
  * *device_status (may be NULL) receives the raw word (bit 0: a mixing
- * parameter outside [0, 1]; bit 1: some nu_i <= 0 or not finite).
- * Returns GNA_E_DOMAIN if any bit was set, else GNA_OK (or GNA_E_HIP).
+ * parameter outside [0, 1]; bit 1: some nu_i <= 0 or not finite; bit 2: a
+ * queued tail gave up waiting for its fit's tiles).
+ * Returns GNA_E_HIP if bit 2 was set (the results of that evaluation are not
+ * valid; gna_plan_rebuild restores the plan), else GNA_E_DOMAIN if any bit
+ * was set, else GNA_OK (or GNA_E_HIP from the runtime).
  */
 int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
 /* Launch shape in use: writes 7 ints (threads, lanes_per_bin, chunks,
  * persistent, smear_mfma, shared_phases, split_tail) and the number of tiles
- * of one evaluation.  shared_phases is 1 when the MFMA kernel lets tiles with
+ * of one evaluation (for the MFMA scan kernel, smear_mfma > 0: its lanes per
+ * work-group, 1, 1, and tiles of 16 points at the plan's max_batch).  shared_phases is 1 when the MFMA kernel lets tiles with
  * common (dm2_21, dm2_31) share their phases: the plan allows it
  * (no_shared_phases = 0) and the shape asks for it (the autotuner tries
  * both).  split_tail is 1 when a fitset runs its tails in separate launches,

@@ -193,6 +193,8 @@ int launch_scan(gna_plan* p, const double* params, int32_t B, double* chi2, doub
                 double* pred, hipStream_t s);
 int build_scan_tables(gna_plan* p, hipStream_t s);
 bool scan_supported(const gna_plan* p);
+// Lanes per work-group of the MFMA scan kernel for this plan (0: it does not fit).
+int scan_threads(const gna_plan* p);
 size_t scan_dense_bytes(const gna_plan* p);
 // Dynamic LDS of the generic kernel: vs = LDS stride of the point's vectors
 // (0: they stay in the scratch region), kf_cap = largest number of diagonal

@@ -981,16 +981,20 @@ extern "C" int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_sta
 extern "C" int gna_plan_shape(const gna_plan* plan, int32_t shape_out[7], int64_t* n_tiles) {
   clear_error();
   if (!plan) return fail(GNA_E_INVAL, "plan is NULL");
+  // The MFMA scan kernel has its own tiling: 16 parameter points per tile,
+  // one work-group of scan_threads lanes each (lanes per bin and chunks do
+  // not apply).
+  const bool mfma = plan->shape.mfma != 0;
   if (shape_out) {
-    shape_out[0] = plan->shape.threads;
-    shape_out[1] = plan->shape.G;
-    shape_out[2] = plan->shape.C;
+    shape_out[0] = mfma ? scan_threads(plan) : plan->shape.threads;
+    shape_out[1] = mfma ? 1 : plan->shape.G;
+    shape_out[2] = mfma ? 1 : plan->shape.C;
     shape_out[3] = plan->shape.persistent;
     shape_out[4] = plan->shape.mfma;
     shape_out[5] = plan->share_phases;
     shape_out[6] = plan->shape.split;
   }
-  if (n_tiles) *n_tiles = plan->n_tiles;
+  if (n_tiles) *n_tiles = mfma ? (int64_t)(plan->n_points + 15) / 16 : plan->n_tiles;
   return GNA_OK;
 }
 

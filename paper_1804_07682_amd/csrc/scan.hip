@@ -769,20 +769,6 @@ ScanLayout scan_layout(const gna_plan* p) {
   return L;
 }
 
-int scan_threads(const gna_plan* p) {
-  const ProbDev& pd = p->probs[0];
-  const int mt = (pd.n_bins + 15) / 16;
-  const int nq = pd.n_bins * pd.ppb;
-  const bool fp64 = p->prec == GNA_FP64;
-  // 512 lanes: the gradient variant keeps mu0 / J0 of 8 bins in registers
-  // (~240 VGPRs in FP64) without spilling; 1024 lanes would cap it at 128.
-  for (int nt : {512}) {
-    const size_t b = fp64 ? scan_lds<double>(pd.n_L, nq, mt, nt / 64, 0, false)
-                          : scan_lds<float>(pd.n_L, nq, mt, nt / 64, 0, false);
-    if (b <= std::min(kScanLdsMax, p->lds_limit)) return nt;
-  }
-  return 0;
-}
 
 template <class R, bool GRAD, int NT, int WPE, bool SHARE>
 int launch_scan_k(gna_plan* p, const ScanArgs<R>& a, const gna_plan::LaunchCache& lc,
@@ -877,6 +863,21 @@ int launch_scan_r(gna_plan* p, const double* params, int32_t B, double* chi2, do
 }
 
 }  // namespace
+
+int scan_threads(const gna_plan* p) {
+  const ProbDev& pd = p->probs[0];
+  const int mt = (pd.n_bins + 15) / 16;
+  const int nq = pd.n_bins * pd.ppb;
+  const bool fp64 = p->prec == GNA_FP64;
+  // 512 lanes: the gradient variant keeps mu0 / J0 of 8 bins in registers
+  // (~240 VGPRs in FP64) without spilling; 1024 lanes would cap it at 128.
+  for (int nt : {512}) {
+    const size_t b = fp64 ? scan_lds<double>(pd.n_L, nq, mt, nt / 64, 0, false)
+                          : scan_lds<float>(pd.n_L, nq, mt, nt / 64, 0, false);
+    if (b <= std::min(kScanLdsMax, p->lds_limit)) return nt;
+  }
+  return 0;
+}
 
 bool scan_supported(const gna_plan* p) {
   if (p->kind != kChain || p->probs.empty()) return false;

@@ -43,7 +43,10 @@ def _eval(plan, P, pred=True, grad=True):
 def test_scan_fp64_parity(cfg0, B):
     P = W.config3_params(8, 8)[:B]
     plan = _plan(cfg0, B)
-    assert plan.shape()["smear_mfma"] == 1
+    shape = plan.shape()
+    assert shape["smear_mfma"] == 1
+    # the scan kernel's own tiling: 512 lanes, 16 points per tile
+    assert shape["threads"] == 512 and shape["n_tiles"] == (B + 15) // 16
     got = _eval(plan, P)
     ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
     assert np.max(rel_err(got["chi2"], ref["chi2"])) <= FP64_RTOL

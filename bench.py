@@ -138,7 +138,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--only", default=None,
                     help="run one workload for profiling: scan|scan64|scan_pp|scan64_pp|pee|pee64|copy|"
-                         "chain1|chain8|fitset")
+                         "chain1|chain8|fitset|fitset1|fitsetq|graph")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the automatic launch shape (no autotuning), for counter runs")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
@@ -429,11 +429,23 @@ def transfer_pipeline(gna, W, torch, dev, n=10 ** 8):
     return res
 
 
+def _median_us(fn, reps):
+    """Median host wall time of fn(i), i < reps, in microseconds (robust to the
+    occasional host-side stall that would dominate a mean)."""
+    t = []
+    for i in range(reps):
+        t0 = time.perf_counter()
+        fn(i)
+        t.append(time.perf_counter() - t0)
+    return float(np.median(t)) * 1e6
+
+
 def graph_lazy(gna, W, torch, dev, reps=200):
     """Transformation graph of the config-0 chain (points -> P_ee -> flux product
     -> bin sums -> smearing -> norm -> chi^2), read back after changing dm2_31
     (every node after the points recomputed) or only the normalisation (two
-    nodes recomputed), against the fused chain for the same evaluation."""
+    nodes recomputed), against the fused chain for the same evaluation, and
+    the graph's fused chain node (chi^2 and gradient) read back."""
     model = W.model()
     pr = W.config0()
     tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
@@ -448,12 +460,11 @@ def graph_lazy(gna, W, torch, dev, reps=200):
     g.bind()
     res = {}
     for tag, var, base in (("dm31_changed", v[1], W.THETA0[1]), ("norm_changed", v[4], 1.0)):
-        g.read(chi2)
-        t0 = time.perf_counter()
-        for i in range(reps):
+        for i in range(10):  # untimed warm-up of this change pattern
             g.set(var, base * (1.0 + 1e-6 * (i % 2 + 1)))
             g.read(chi2)
-        res[f"{tag}_us"] = (time.perf_counter() - t0) / reps * 1e6
+        res[f"{tag}_us"] = _median_us(
+            lambda i: (g.set(var, base * (1.0 + 1e-6 * (i % 2 + 1))), g.read(chi2)), reps)
     plan = gna.Chain(pr, model, max_batch=1, device=dev, opts={"smear_mfma": 0})
     P = torch.tensor(W.THETA0, device=dev).reshape(1, 5)
     out = {"chi2": torch.empty(1, dtype=torch.float64, device=dev)}
@@ -463,11 +474,34 @@ def graph_lazy(gna, W, torch, dev, reps=200):
         host.copy_(out["chi2"], non_blocking=True)
         torch.cuda.current_stream().synchronize()
     fused()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fused()
-    res["fused_chain_us"] = (time.perf_counter() - t0) / reps * 1e6
-    res["note"] = "chi^2 read back to the host each time (one synchronising copy per evaluation)"
+    res["fused_chain_us"] = _median_us(lambda i: fused(), reps)
+    out6 = torch.empty(6, dtype=torch.float64, device=dev)
+    host6 = torch.empty(6, dtype=torch.float64).pin_memory()
+    outg = {"chi2": out6[:1], "grad": out6[1:].view(1, 5)}
+    def fused_grad():
+        plan.eval(P, grad=True, out=outg)
+        host6.copy_(out6, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+    fused_grad()
+    res["fused_chain_grad_us"] = _median_us(lambda i: fused_grad(), reps)
+    g.close()
+    # The same evaluation as one fused chain node of a graph (chi^2 and its
+    # gradient in one launch), after a dm2_31 change and with nothing changed
+    # (the read returns the host mirror; no launch, no copy).
+    g = gna.Graph(dev)
+    v = [g.variable(nm, W.THETA0[i]) for i, nm in enumerate(("dm21", "dm31", "s12", "s13", "norm"))]
+    pts = g.points(pr, model)
+    node = g.chain(pts, v, "fp64")
+    g.bind()
+    for i in range(10):  # untimed warm-up
+        g.set(v[1], W.THETA0[1] * (1.0 + 1e-6 * (i % 2 + 1)))
+        g.read(node)
+    res["chain_node_dm31_changed_us"] = _median_us(
+        lambda i: (g.set(v[1], W.THETA0[1] * (1.0 + 1e-6 * (i % 2 + 1))), g.read(node)), reps)
+    res["chain_node_unchanged_us"] = _median_us(lambda i: g.read(node), reps)
+    res["note"] = ("host wall time per evaluation, median of the repetitions; chi^2 read "
+                   "back to the host each time (one synchronising copy per evaluation); the "
+                   "chain node also returns the gradient")
     g.close()
     return res
 
@@ -622,6 +656,8 @@ def main():
             r = bench_pee(gna, W, torch, timer, dev, 10 ** 8, 52.5,
                           "fp64" if o == "pee64" else "mixed", args.steps)
             log(f"{o}: {r}")
+        elif o == "graph":
+            log(f"graph: {graph_lazy(gna, W, torch, dev)}")
         elif o == "copy":
             log(f"copy probe: {copy_probe(gna, torch, timer, dev, steps=args.steps)}")
         elif o == "chain1":

@@ -170,7 +170,17 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     td.chunk = local - td.bb * p0.C;
   }
   const ProbDev pd = a.probs[td.prob];
-  const double* th = a.params + 5 * (int64_t)td.point;
+  // The point's parameters (uniform over the work-group): from the device
+  // array, or passed by value for a single point.
+  double thv[5];
+  if (a.params) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) thv[c] = a.params[5 * (int64_t)td.point + c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) thv[c] = a.pin[c];
+  }
+  const double* th = thv;
   for (int r = tid; r < pd.n_L; r += NT) {
     bl.kl[r] = kPhase * a.L[pd.L_off + r];
     bl.w[r] = a.wL[pd.L_off + r];
@@ -889,10 +899,15 @@ int launch_queued(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
 
 template <class R>
 int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
-             double* pred, hipStream_t s) {
+             double* pred, hipStream_t s, const double* host_params) {
   unsigned char* w = p->ws;
   const Layout& L = p->lay;
   ChainArgs<R> a{};
+  if (!params) {
+    if (B != 1 || !host_params || p->kind != kChain)
+      return fail(GNA_E_INVAL, "parameters by value: one point of a chain plan only");
+    for (int c = 0; c < 5; ++c) a.pin[c] = host_params[c];
+  }
   a.probs = (const ProbDev*)(w + L.probs);
   if (p->kind == kChain) {
     a.tiles = nullptr;
@@ -949,9 +964,9 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
 }  // namespace
 
 int launch_chain(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
-                 double* pred, hipStream_t s) {
-  if (p->prec == GNA_FP64) return launch_r<double>(p, params, B, chi2, grad, pred, s);
-  return launch_r<float>(p, params, B, chi2, grad, pred, s);
+                 double* pred, hipStream_t s, const double* host_params) {
+  if (p->prec == GNA_FP64) return launch_r<double>(p, params, B, chi2, grad, pred, s, host_params);
+  return launch_r<float>(p, params, B, chi2, grad, pred, s, host_params);
 }
 
 }  // namespace gna

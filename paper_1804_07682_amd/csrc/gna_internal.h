@@ -79,7 +79,8 @@ struct ChainArgs {
   const double* data;
   const SliceDev* slices;
   const R* Rv;
-  const double* params;
+  const double* params;      // [B][5] on the device; NULL: one point, given in pin
+  double pin[5];             // the one point's parameters, by value (params == NULL)
   R* scratch;
   uint32_t* counters;
   uint32_t* status;
@@ -187,8 +188,10 @@ void clear_error();
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Launch helpers implemented in the .hip files.
+// params: [B][5] on the device, or NULL with B = 1 and the point's five
+// parameters in host_params (passed by value to the kernel: no upload).
 int launch_chain(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
-                 double* pred, hipStream_t s);
+                 double* pred, hipStream_t s, const double* host_params = nullptr);
 int launch_scan(gna_plan* p, const double* params, int32_t B, double* chi2, double* grad,
                 double* pred, hipStream_t s);
 int build_scan_tables(gna_plan* p, hipStream_t s);

@@ -567,12 +567,19 @@ int compute_gpu(gna_graph* g, int id, hipStream_t s) {
     }
     case kChainNode: {
       const Geometry& ge = g->geoms[nd.geom];
-      double* params = (double*)(g->ws + nd.aux_off);
-      hipLaunchKernelGGL(params_kernel, dim3(1), dim3(64), 0, s, params, var(g, nd, 0),
-                         var(g, nd, 1), var(g, nd, 2), var(g, nd, 3), var(g, nd, 4));
-      if ((rc = check_hip(hipGetLastError(), "graph chain parameters"))) return rc;
       gna_plan* p = nd.prec == GNA_FP64 ? ge.plan : ge.plan_mixed;
-      if ((rc = gna_chain_eval(p, params, 1, out, out + 1, nullptr, s))) return rc;
+      if (!p->shape.mfma) {
+        // One point: its parameters go to the kernel by value, no upload.
+        const double th[5] = {var(g, nd, 0), var(g, nd, 1), var(g, nd, 2), var(g, nd, 3),
+                              var(g, nd, 4)};
+        if ((rc = launch_chain(p, nullptr, 1, out, out + 1, nullptr, s, th))) return rc;
+      } else {
+        double* params = (double*)(g->ws + nd.aux_off);
+        hipLaunchKernelGGL(params_kernel, dim3(1), dim3(64), 0, s, params, var(g, nd, 0),
+                           var(g, nd, 1), var(g, nd, 2), var(g, nd, 3), var(g, nd, 4));
+        if ((rc = check_hip(hipGetLastError(), "graph chain parameters"))) return rc;
+        if ((rc = gna_chain_eval(p, params, 1, out, out + 1, nullptr, s))) return rc;
+      }
       break;
     }
     case kPoints:

@@ -709,10 +709,14 @@ class Graph:
         return None if self.workspace is None else _stream(self.device)
 
     def read(self, node: int) -> np.ndarray:
-        n = self.info(node)["n"]
+        # A node's length never changes once the node exists: ask the library once.
+        sizes = self.__dict__.setdefault("_sizes", {})
+        n = sizes.get(node)
+        if n is None:
+            n = sizes[node] = self.info(node)["n"]
         out = np.empty(n, dtype=np.float64)
-        check(load().gna_graph_read(self._g, node, _dptr(out), n, self._graph_stream()),
-              "gna_graph_read")
+        stream = None if self.workspace is None else _raw_stream(self.device)
+        check(load().gna_graph_read(self._g, node, _dptr(out), n, stream), "gna_graph_read")
         return out
 
     def eval(self, node: int) -> torch.Tensor:

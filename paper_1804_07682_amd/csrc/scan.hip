@@ -25,6 +25,10 @@ namespace gna {
 namespace {
 
 constexpr int kScanN = 16;         // parameter points per tile (MFMA N)
+// Row stride of the GEMM operand bb in LDS: 16 columns and one of padding,
+// so that rows written by neighbouring lanes (one bin each) start in
+// different banks, and the MFMA operand reads (4 rows of 16) stay spread.
+constexpr int kBRow = 17;
 constexpr int kScanMaxBins = 256;  // 16 row tiles of 16
 constexpr size_t kScanLdsMax = 64 * 1024;
 
@@ -80,7 +84,7 @@ __device__ __forceinline__ void gemm_row_global(const R* __restrict__ At, int lo
       const int kb = kb0 + b;
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+        const R bv = bb[(kb * 16 + st * 4 + krow) * kBRow + n];
         acc = Acc<R>::mfma(av[b][st], bv, acc);
       }
     }
@@ -173,9 +177,10 @@ __host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, i
                                            bool share) {
   return a16((size_t)scan_meta_ints(mt) * 4) + a16((size_t)kScanN * 5 * 8) +
          a16((size_t)nL * nq * 8) + a16((size_t)nq * sizeof(R)) + a16((size_t)mt * 16 * 8) +
-         a16((size_t)nL * 8) + a16((size_t)mt * 16 * kScanN * sizeof(R)) +
+         a16((size_t)nL * 8) + a16((size_t)mt * 16 * kBRow * sizeof(R)) +
          a16((size_t)nwaves * kScanN * 6 * 8) + (share ? a16((size_t)mt * 16 * kTab * 8) : 0) +
-         a16((size_t)kLogTab * 16) + a16((size_t)rblocks * kBlk * sizeof(R));
+         (sizeof(R) == 4 ? a16((size_t)kLogTab * 16) : 0) +
+         a16((size_t)rblocks * kBlk * sizeof(R));
 }
 
 template <class T>
@@ -229,14 +234,14 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   cur += a16((size_t)nbp * 8);
   double* w_s = reinterpret_cast<double*>(cur);
   cur += a16((size_t)nL * 8);
-  R* bb = reinterpret_cast<R*>(cur);  // [nbp][16] GEMM B operand
-  cur += a16((size_t)nbp * kScanN * sizeof(R));
+  R* bb = reinterpret_cast<R*>(cur);  // [nbp][kBRow] GEMM B operand (16 columns used)
+  cur += a16((size_t)nbp * kBRow * sizeof(R));
   double* red = reinterpret_cast<double*>(cur);  // [NW][16][6]
   cur += a16((size_t)NW * kScanN * 6 * 8);
   double* mm = reinterpret_cast<double*>(cur);  // [nbp][kTab] M = R T of a shared tile
   cur += SHARE ? a16((size_t)nbp * kTab * 8) : 0;
   double* lt_s = reinterpret_cast<double*>(cur);  // [kLogTab][2] logarithm table
-  cur += a16((size_t)kLogTab * 16);
+  cur += sizeof(R) == 4 ? a16((size_t)kLogTab * 16) : 0;  // FP32 kernels only
   R* Rs = reinterpret_cast<R*>(cur);  // [nblk][16][kRowPad] the band of R (if a.rlds)
 
   const int tid = threadIdx.x;
@@ -260,7 +265,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
   if (sizeof(R) == 4) copy16<NT>(lt_s, a.logtab, (size_t)kLogTab * 16);
   // The GEMM operand starts at zero (its padding rows and, for shared tiles,
   // columns kTab..15 stay zero until a per-point tile writes them).
-  for (int i = tid; i < nbp * kScanN; i += NT) bb[i] = R(0);
+  for (int i = tid; i < nbp * kBRow; i += NT) bb[i] = R(0);
   __syncthreads();
   // The band is needed only from the smearing on: its copy runs while the
   // point pass computes (issued after the barrier, which would wait for it).
@@ -359,25 +364,16 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
         if (j < nb && sub == 0) {
           // Row j of the operand in 16-byte stores (fewer, wider LDS writes
           // than one per sum: the rows of neighbouring lanes share banks).
-          R* row = bb + j * kScanN;
-          if constexpr (sizeof(R) == 4) {
-            using V4 = float __attribute__((ext_vector_type(4)));
-            using V2 = float __attribute__((ext_vector_type(2)));
-            reinterpret_cast<V4*>(row)[0] = V4{sum[0], sum[1], sum[2], sum[3]};
-            reinterpret_cast<V4*>(row)[1] = V4{sum[4], sum[5], sum[6], sum[7]};
-            reinterpret_cast<V2*>(row)[4] = V2{sum[8], sum[9]};
-          } else {
-            using D2 = double __attribute__((ext_vector_type(2)));
+          R* row = bb + j * kBRow;
 #pragma unroll
-            for (int c = 0; c < kTab; c += 2) reinterpret_cast<D2*>(row)[c / 2] = D2{sum[c], sum[c + 1]};
-          }
+          for (int c = 0; c < kTab; ++c) row[c] = sum[c];
         }
       }
       // The rest of the operand (columns kTab..15) is zero unless a per-point
       // tile of this work-group wrote it.
       if (!bb_clean) {
-        for (int i = tid; i < nb * kScanN; i += NT)
-          if ((i & (kScanN - 1)) >= kTab) bb[i] = R(0);
+        for (int i = tid; i < nb * kBRow; i += NT)
+          if (i % kBRow >= kTab) bb[i] = R(0);
         bb_clean = true;
       }
     } else {
@@ -418,7 +414,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) J0[m][c] = J[c];
         }
-        if (j < nbp) bb[j * kScanN + n] = (R)norm * mu;  // padded rows: 0
+        if (j < nbp) bb[j * kBRow + n] = (R)norm * mu;  // padded rows: 0
       }
       bb_clean = false;
     }
@@ -440,7 +436,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
               const R av = Ab[(kb - lo) * kBlk + 4 * st];
-              const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+              const R bv = bb[(kb * 16 + st * 4 + krow) * kBRow + n];
               acc[u] = Acc<R>::mfma(av, bv, acc[u]);
             }
           }
@@ -548,7 +544,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             const double ratio = quot_pos(d, nu);
             const double term = dfma(d, chi2_log<R>(d > 0.0 ? ratio : 1.0, lt_s), nu - d);
             chi += in ? term : 0.0;
-            bb[i * kScanN + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
+            bb[i * kBRow + n] = in ? (R)(2.0 * (1.0 - ratio)) : R(0);
           }
         }
       }
@@ -592,7 +588,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                   const R av = Ab[4 * st * kRowPad];
-                  const R bv = bb[(kb * 16 + st * 4 + krow) * kScanN + n];
+                  const R bv = bb[(kb * 16 + st * 4 + krow) * kBRow + n];
                   acc2[u] = Acc<R>::mfma(av, bv, acc2[u]);
                 }
               }
@@ -608,7 +604,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
           const int J = wave + u * NW;
           if (J < mt) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) bb[(J * 16 + Acc<R>::row(krow, v)) * kScanN + n] = acc2[u][v];
+            for (int v = 0; v < 4; ++v) bb[(J * 16 + Acc<R>::row(krow, v)) * kBRow + n] = acc2[u][v];
           }
         }
         __syncthreads();
@@ -636,7 +632,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) J[c] = rfma_t<R>(fk, dpb[c], J[c]);
               }
-              const double gm = (double)bb[j * kScanN + n];
+              const double gm = (double)bb[j * kBRow + n];
 #pragma unroll
               for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J[c], g[c]);
               g[4] = dfma(gm, (double)mu0[m], g[4]);
@@ -647,7 +643,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
           for (int m = 0; m < PPT; ++m) {
             const int j = bg + NG * m;
             if (j < nb) {
-              const double gm = (double)bb[j * kScanN + n];
+              const double gm = (double)bb[j * kBRow + n];
 #pragma unroll
               for (int c = 0; c < 4; ++c) g[c] = dfma(gm, (double)J0[m][c], g[c]);
               g[4] = dfma(gm, (double)mu0[m], g[4]);

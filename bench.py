@@ -143,7 +143,7 @@ def parse():
                     help="keep the automatic launch shape (no autotuning), for counter runs")
     ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--opts", default=None,
-                    help="with --only fitset*: launch options as JSON, e.g. "
+                    help="with --only fitset* / chain1 / chain8: launch options as JSON, e.g. "
                          "'{\"split_tail\": 2, \"threads\": 128}' (no autotuning)")
     return ap.parse_args()
 
@@ -279,17 +279,18 @@ def copy_probe(gna, torch, timer, dev, n=10 ** 8, steps=20):
     return {"GBps": 16 * n / kmean / 1e9, "bytes": 16 * n, "kernel_ms": kmean * 1e3}
 
 
-def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec):
+def bench_chain_single(gna, W, torch, timer, dev, problem_fn, seed, steps, prec, opts=None):
     model = W.model()
     pr = problem_fn()
     tmp = gna.Chain(pr, model, max_batch=1, prec="fp64", opts={"smear_mfma": 0}, device=dev)
     nu = tmp.eval(torch.tensor(W.THETA0, device=dev).reshape(1, 5), grad=False,
                   pred=True)["pred"].cpu().numpy()[0]
     pr["data"] = W.poisson_counts(nu, seed)
-    plan = gna.Chain(pr, model, max_batch=1, prec=prec, device=dev)
+    plan = gna.Chain(pr, model, max_batch=1, prec=prec, device=dev, opts=opts)
     P = torch.tensor(W.THETA0 * np.array([1.01, 0.99, 1.02, 0.97, 1.0]),
                      device=dev).reshape(1, 5)
-    plan.autotune(P, reps=5)
+    if opts is None:
+        plan.autotune(P, reps=5)
     out = {"chi2": torch.empty(1, dtype=torch.float64, device=dev),
            "grad": torch.empty((1, 5), dtype=torch.float64, device=dev)}
     wall, kpair, _ = timer.run(lambda: plan.eval(P, grad=True, out=out), steps, 10)
@@ -662,10 +663,11 @@ def main():
             log(f"copy probe: {copy_probe(gna, torch, timer, dev, steps=args.steps)}")
         elif o == "chain1":
             log(str(bench_chain_single(gna, W, torch, timer, dev, W.config0, W.SEED, args.steps,
-                                       args.prec)))
+                                       args.prec, json.loads(args.opts) if args.opts else None)))
         elif o == "chain8":
             log(str(bench_chain_single(gna, W, torch, timer, dev, W.config2, W.SEED + 2,
-                                       args.steps, args.prec)))
+                                       args.steps, args.prec,
+                                       json.loads(args.opts) if args.opts else None)))
         elif o in ("fitset", "fitset1", "fitsetq"):
             opts = {"fitset1": {"split_tail": 1, "persistent": 1},
                     "fitsetq": {"split_tail": 3, "persistent": 1}}.get(o)

@@ -256,18 +256,22 @@ typedef struct gna_problem {
  *                  rounding, so a point's last bits may depend on its tile
  *                  neighbours.  1: every point evaluates its own phases, and
  *                  its result does not depend on the rest of the batch.
- *   split_tail     (fitset plans only) 0: automatic; 1: each fit's tail
+ *   split_tail     0: automatic; 1: each point's (fit's) tail
  *                  (smearing, chi^2, gradient) runs in the work-group that
- *                  finishes the fit's last tile; 2: the point pass only
- *                  stores bin sums, and two more launches run the tails of
- *                  all fits with one wavefront per 64-row slice, then add
- *                  each fit's partials in a fixed order; 3: queued tail,
- *                  one launch: the persistent queue holds the point tiles
- *                  and, some way after each fit's last tile, that fit's
- *                  tail (one work-group waits for the fit's tiles, then runs
- *                  its slices and the fixed-order sum; implies
- *                  persistent = 1; same results as 2, bit for bit).  A
- *                  nonzero value also keeps gna_plan_autotune to that tail.
+ *                  finishes its last tile; 2: the point pass only stores bin
+ *                  sums and the tails run in later launches: for a chain
+ *                  plan one work-group per parameter point (the same sums in
+ *                  the same order as 1, bit for bit; the default when a
+ *                  point has several tiles), for a fitset two launches with
+ *                  one wavefront per 64-row slice, then each fit's partials
+ *                  added in a fixed order (the fitset default); 3 (fitset
+ *                  plans only): queued tail, one launch: the persistent
+ *                  queue holds the point tiles and, some way after each
+ *                  fit's last tile, that fit's tail (one work-group waits for
+ *                  the fit's tiles, then runs its slices and the fixed-order
+ *                  sum; implies persistent = 1; same results as 2, bit for
+ *                  bit).  A nonzero value also keeps gna_plan_autotune to
+ *                  that tail.
  */
 typedef struct gna_launch_opts {
   int32_t threads;
@@ -353,8 +357,8 @@ int gna_plan_status(gna_plan* plan, void* stream, int32_t* device_status);
  * work-group, 1, 1, and tiles of 16 points at the plan's max_batch).  shared_phases is 1 when the MFMA kernel lets tiles with
  * common (dm2_21, dm2_31) share their phases: the plan allows it
  * (no_shared_phases = 0) and the shape asks for it (the autotuner tries
- * both).  split_tail is 1 when a fitset runs its tails in separate launches,
- * 2 when it queues them in its one persistent launch. */
+ * both).  split_tail is 1 when the tails run in launches after the point
+ * pass, 2 when a fitset queues them in its one persistent launch. */
 int gna_plan_shape(const gna_plan* plan, int32_t shape_out[7], int64_t* n_tiles);
 /*
  * Project-written autotuner: times each candidate launch shape of this plan

@@ -154,6 +154,149 @@ struct BaseLds {
   double w[kMaxBaselines];   // w_r
 };
 
+// The tail of one point (a fit, for a fitset) once its bin sums are
+// complete: the chunk sums (unless the point was one tile whose sums are
+// already in LDS), nu = norm R mu0 with the four tangent columns through R,
+// the chi^2 terms, the gradient, in one work-group.  vl / sc: the point's
+// vectors in LDS (L.vs > 0) or in chunk 0 of its scratch region.
+template <class R, bool GRAD>
+__device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, const double* th,
+                           bool bad, const TileLds& L, bool single) {
+  const int tid = threadIdx.x;
+  const int NT = blockDim.x;
+  const int nb = pd.n_bins;
+  const bool vlds = L.vs > 0;
+  R* vl = L.vec<R>();
+  R* sc = a.scratch + (a.tiles ? pd.scratch_off : (int64_t)point * a.scratch_stride);
+  // ---- tail ----------------------------------------------------------------
+  constexpr int NC = GRAD ? 5 : 1;
+  const int C = pd.C;
+  const double* dat = a.data + pd.bin_off;
+  // This thread's first row of the chi^2 pass below when the slices are
+  // split into chunks (row tid); requested now so that its latency overlaps.
+  const double d_first = (tid < nb) ? dat[tid] : 0.0;
+  // Entries e = c nb + jj of the NC vectors, two per trip so that two
+  // entries' chunk loads are in flight together.
+  if (vlds) {
+    if (!single) {
+#pragma unroll 2
+      for (int e = tid; e < NC * nb; e += NT) {
+        const int c = e / nb, jj = e - (e / nb) * nb;
+        vl[c * L.vs + jj] = sum_chunks<R>(sc, C, c, nb, jj);
+      }
+    }
+  } else if (C > 1) {
+    // In place into chunk 0: each entry is read and written by one thread.
+#pragma unroll 2
+    for (int e = tid; e < NC * nb; e += NT) {
+      const int c = e / nb, jj = e - (e / nb) * nb;
+      const R v = sum_chunks<R>(sc, C, c, nb, jj);
+      sc[c * nb + jj] = v;
+    }
+  }
+  __syncthreads();
+
+  const double norm = th[4];
+  const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
+  const int nwaves = NT / kWave;
+  const int ns = pd.n_slices;
+  const SliceDev* slices = a.slices + pd.slice_off;
+  double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)point * nb)
+                        : nullptr;
+  double chi = 0.0;
+  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  bool badnu = false;
+  // Row i (data d) from s_i = acc[0] and t_ic = acc[1 + c].
+  auto finish = [&](int i, double d, const R(&acc)[NC]) {
+    const double nu = norm * (double)acc[0];
+    if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
+    const double ratio = quot_pos(d, nu);
+    chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
+    if (GRAD) {
+      const double gn = 2.0 * (1.0 - ratio);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gs[c] = dfma(gn, (double)acc[(1 + c) % NC], gs[c]);
+      gs[4] = dfma(gn, (double)acc[0], gs[4]);
+    }
+    if (pred) pred[i] = nu;
+  };
+
+  // Smearing: work items (slice, chunk of its diagonals) over all waves.  With
+  // one chunk per slice each wavefront finishes its own rows.
+  const int Kf = min(L.kf_cap, max(1, nwaves / ns));
+  const int PS = ns * kSlice;
+  R* part = L.part<R>();  // [Kf][NC][PS]: Kf * PS <= threads
+  for (int item = wave; item < ns * Kf; item += nwaves) {
+    const int s = item / Kf, kap = item - (item / Kf) * Kf;
+    const SliceDev sd = slices[s];
+    const int csz = (sd.nd + Kf - 1) / Kf;
+    const int d0 = min(sd.nd, kap * csz), d1 = min(sd.nd, d0 + csz);
+    const int i = s * kSlice + lane;
+    const double di = (Kf == 1 && i < nb) ? dat[i] : 0.0;
+    R acc[NC];
+    if (vlds)
+      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, vl, L.vs, d0, d1, acc);
+    else
+      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, sc, nb, d0, d1, acc);
+    if (i < nb) {
+      if (Kf == 1) {
+        finish(i, di, acc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) part[(kap * NC + c) * PS + i] = acc[c];
+      }
+    }
+  }
+  if (Kf > 1) {
+    __syncthreads();
+    for (int i = tid; i < nb; i += NT) {
+      R acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = part[c * PS + i];
+      for (int kap = 1; kap < Kf; ++kap) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += part[(kap * NC + c) * PS + i];
+      }
+      finish(i, i == tid ? d_first : dat[i], acc);
+    }
+  }
+  if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+  double* red = L.red<R>();
+  chi = wave_sum(chi);
+  if (GRAD) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
+  }
+  if (lane == 0) {
+    red[wave * 6] = chi;
+    if (GRAD) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) red[wave * 6 + 1 + c] = gs[c];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < nwaves; ++w) {
+      chisum += red[w * 6];
+      if (GRAD) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) g5[c] += red[w * 6 + 1 + c];
+      }
+    }
+    if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    a.chi2[point] = bad ? NAN : 2.0 * chisum;
+    if (GRAD && a.grad) {
+      double* gp = a.grad + 5 * (int64_t)point;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * g5[c];
+      gp[4] = bad ? NAN : g5[4];
+    }
+  }
+}
+
 template <class R, bool GRAD, bool SPLIT, bool QUEUED = false>
 __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L, BaseLds& bl) {
   const int tid = threadIdx.x;
@@ -279,11 +422,12 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
   const int nb = pd.n_bins;
   if (SPLIT) {
     // Split tail: every tile leaves its partial sums in the scratch region;
-    // the tail kernels read them after this launch.  Queued tail: the tile
+    // the tail kernels (a fitset's, or a chain plan's per-point tail) read
+    // them after this launch.  Queued tail: the tile
     // then counts itself done for its fit, releasing its sums at agent scope
     // (every wavefront's stores acknowledged first, one L2 write-back by the
     // release-ordered increment), for the tail items of the same launch.
-    R* sc = a.scratch + pd.scratch_off;
+    R* sc = a.scratch + (a.tiles ? pd.scratch_off : (int64_t)td.point * a.scratch_stride);
     if (g == 0 && lb < pd.bins_per_tile && j < nb) {
       sc[(int64_t)(td.chunk * 5) * nb + j] = mu;
       if (GRAD) {
@@ -344,134 +488,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     __syncthreads();
   }
 
-  // ---- tail ----------------------------------------------------------------
-  constexpr int NC = GRAD ? 5 : 1;
-  const int C = pd.C;
-  const double* dat = a.data + pd.bin_off;
-  // This thread's first row of the chi^2 pass below when the slices are
-  // split into chunks (row tid); requested now so that its latency overlaps.
-  const double d_first = (tid < nb) ? dat[tid] : 0.0;
-  // Entries e = c nb + jj of the NC vectors, two per trip so that two
-  // entries' chunk loads are in flight together.
-  if (vlds) {
-    if (!single) {
-#pragma unroll 2
-      for (int e = tid; e < NC * nb; e += NT) {
-        const int c = e / nb, jj = e - (e / nb) * nb;
-        vl[c * L.vs + jj] = sum_chunks<R>(sc, C, c, nb, jj);
-      }
-    }
-  } else if (C > 1) {
-    // In place into chunk 0: each entry is read and written by one thread.
-#pragma unroll 2
-    for (int e = tid; e < NC * nb; e += NT) {
-      const int c = e / nb, jj = e - (e / nb) * nb;
-      const R v = sum_chunks<R>(sc, C, c, nb, jj);
-      sc[c * nb + jj] = v;
-    }
-  }
-  __syncthreads();
-
-  const double norm = th[4];
-  const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
-  const int nwaves = NT / kWave;
-  const int ns = pd.n_slices;
-  const SliceDev* slices = a.slices + pd.slice_off;
-  double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)td.point * nb)
-                        : nullptr;
-  double chi = 0.0;
-  double gs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  bool badnu = false;
-  // Row i (data d) from s_i = acc[0] and t_ic = acc[1 + c].
-  auto finish = [&](int i, double d, const R(&acc)[NC]) {
-    const double nu = norm * (double)acc[0];
-    if (!(nu > 0.0) || !isfinite(nu)) badnu = true;
-    const double ratio = quot_pos(d, nu);
-    chi += dfma(d, log_pos(d > 0.0 ? ratio : 1.0), nu - d);  // d = 0 takes ln 1 = 0
-    if (GRAD) {
-      const double gn = 2.0 * (1.0 - ratio);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) gs[c] = dfma(gn, (double)acc[(1 + c) % NC], gs[c]);
-      gs[4] = dfma(gn, (double)acc[0], gs[4]);
-    }
-    if (pred) pred[i] = nu;
-  };
-
-  // Smearing: work items (slice, chunk of its diagonals) over all waves.  With
-  // one chunk per slice each wavefront finishes its own rows.
-  const int Kf = min(L.kf_cap, max(1, nwaves / ns));
-  const int PS = ns * kSlice;
-  R* part = L.part<R>();  // [Kf][NC][PS]: Kf * PS <= threads
-  for (int item = wave; item < ns * Kf; item += nwaves) {
-    const int s = item / Kf, kap = item - (item / Kf) * Kf;
-    const SliceDev sd = slices[s];
-    const int csz = (sd.nd + Kf - 1) / Kf;
-    const int d0 = min(sd.nd, kap * csz), d1 = min(sd.nd, d0 + csz);
-    const int i = s * kSlice + lane;
-    const double di = (Kf == 1 && i < nb) ? dat[i] : 0.0;
-    R acc[NC];
-    if (vlds)
-      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, vl, L.vs, d0, d1, acc);
-    else
-      slice_dot<R, NC>(a.Rv, sd, s, lane, nb, sc, nb, d0, d1, acc);
-    if (i < nb) {
-      if (Kf == 1) {
-        finish(i, di, acc);
-      } else {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) part[(kap * NC + c) * PS + i] = acc[c];
-      }
-    }
-  }
-  if (Kf > 1) {
-    __syncthreads();
-    for (int i = tid; i < nb; i += NT) {
-      R acc[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = part[c * PS + i];
-      for (int kap = 1; kap < Kf; ++kap) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += part[(kap * NC + c) * PS + i];
-      }
-      finish(i, i == tid ? d_first : dat[i], acc);
-    }
-  }
-  if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-  double* red = L.red<R>();
-  chi = wave_sum(chi);
-  if (GRAD) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
-  }
-  if (lane == 0) {
-    red[wave * 6] = chi;
-    if (GRAD) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) red[wave * 6 + 1 + c] = gs[c];
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double chisum = 0.0, g5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int w = 0; w < nwaves; ++w) {
-      chisum += red[w * 6];
-      if (GRAD) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) g5[c] += red[w * 6 + 1 + c];
-      }
-    }
-    const bool bad = k.bad;
-    if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    a.chi2[td.point] = bad ? NAN : 2.0 * chisum;
-    if (GRAD && a.grad) {
-      double* gp = a.grad + 5 * (int64_t)td.point;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) gp[c] = bad ? NAN : norm * g5[c];
-      gp[4] = bad ? NAN : g5[4];
-    }
-  }
+  point_tail<R, GRAD>(a, pd, td.point, th, k.bad, L, single);
 }
 
 template <class R, bool GRAD, bool PERSIST, bool SPLIT>
@@ -518,6 +535,28 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int vs, int
 // Carrying the four tangent columns through the smearing replaces the
 // adjoint pass over R^T: sum_j gmu_j J0_jc = sum_i gnu_i (R J0)_ic, so the
 // band is read once per evaluation instead of twice.
+// Two-launch form of a chain plan (split tail): after the point pass of all
+// tiles, one work-group per parameter point sums the point's chunks and runs
+// its tail.  The launch boundary orders the sums; there is no completion
+// counter and no cross-work-group release, which a one-launch hand-off pays
+// in every tile (an L2 write-back, then an atomic round trip).
+template <class R, bool GRAD>
+__global__ void __launch_bounds__(1024) chain_tail_kernel(ChainArgs<R> a, int vs, int kf_cap) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  TileLds L{lds_raw, (int)blockDim.x, vs, kf_cap};
+  const int point = blockIdx.x;
+  double th[5];
+  if (a.params) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) th[c] = a.params[5 * (int64_t)point + c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) th[c] = a.pin[c];
+  }
+  const bool bad = pee_coef<R>(th).bad;
+  point_tail<R, GRAD>(a, a.probs[0], point, th, bad, L, false);
+}
+
 template <class R>
 struct TailArgs {
   const ProbDev* probs;
@@ -868,6 +907,19 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   return check_hip(hipGetLastError(), "chain_kernel launch");
 }
 
+template <class R>
+int launch_point_tails(gna_plan* p, const ChainArgs<R>& a, int32_t B, bool grad, hipStream_t s) {
+  const Shape& sh = p->shape;
+  const ChainLds cl = chain_lds(p, sh);  // the fused tail's LDS (vectors, partials, reductions)
+  if (grad)
+    hipLaunchKernelGGL((chain_tail_kernel<R, true>), dim3((unsigned)B), dim3(sh.threads), cl.bytes,
+                       s, a, cl.vs, cl.kf_cap);
+  else
+    hipLaunchKernelGGL((chain_tail_kernel<R, false>), dim3((unsigned)B), dim3(sh.threads),
+                       cl.bytes, s, a, cl.vs, cl.kf_cap);
+  return check_hip(hipGetLastError(), "chain_tail_kernel launch");
+}
+
 template <class R, bool GRAD>
 int launch_queued(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
   const Shape& sh = p->shape;
@@ -953,6 +1005,7 @@ int launch_r(gna_plan* p, const double* params, int32_t B, double* chi2, double*
     else
       rc = pers ? launch_t<R, false, true, true>(p, a, s) : launch_t<R, false, false, true>(p, a, s);
     if (rc) return rc;
+    if (p->kind == kChain) return launch_point_tails<R>(p, a, B, grad != nullptr, s);
     return launch_tail<R>(p, a, grad != nullptr, s);
   }
   if (grad) {

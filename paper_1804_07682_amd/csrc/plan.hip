@@ -376,7 +376,7 @@ std::vector<Shape> shape_candidates(const gna_plan* p) {
         // Beyond one point per lane the lanes split (point, baseline) items.
         if (C > p->ccap || C > ppb * nL / G + 1) continue;
         for (int pers = 0; pers <= 1; ++pers)
-          for (int split = 0; split <= (p->kind == kFitset ? 2 : 0); ++split) {
+          for (int split = 0; split <= (p->kind == kFitset ? 2 : 1); ++split) {
             if (split == 2 && !pers) continue;  // the queued tail is a persistent launch
             Shape sh;
             sh.threads = t;
@@ -469,8 +469,8 @@ int apply_shape(gna_plan* p, const Shape& sh, hipStream_t s) {
   if (sh.G < 1 || sh.G > kWave || (sh.G & (sh.G - 1)) || sh.G > sh.threads)
     return fail(GNA_E_INVAL, "lanes_per_bin = %d invalid", sh.G);
   if (sh.C < 1) return fail(GNA_E_INVAL, "chunks = %d invalid", sh.C);
-  if (sh.split && p->kind != kFitset)
-    return fail(GNA_E_UNSUPPORTED, "a split tail needs a fitset plan");
+  if (sh.split == 2 && p->kind != kFitset)
+    return fail(GNA_E_UNSUPPORTED, "a queued tail needs a fitset plan");
   if (sh.split == 2 && !sh.persistent)
     return fail(GNA_E_UNSUPPORTED, "a queued tail needs the persistent launch");
   if (sh.mfma && !(p->kind == kChain && scan_supported(p)))
@@ -646,8 +646,8 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
       return fail(GNA_E_INVAL, "opts.no_shared_phases = %d not 0/1", opts->no_shared_phases);
     if (opts->split_tail < 0 || opts->split_tail > 3)
       return fail(GNA_E_INVAL, "opts.split_tail = %d not in 0..3", opts->split_tail);
-    if (opts->split_tail >= 2 && kind != kFitset)
-      return fail(GNA_E_INVAL, "opts.split_tail = %d needs a fitset plan", opts->split_tail);
+    if (opts->split_tail == 3 && kind != kFitset)
+      return fail(GNA_E_INVAL, "opts.split_tail = 3 needs a fitset plan");
   }
   for (int i = 0; i < n_probs; ++i) {
     rc = validate_problem(problems + i, i);
@@ -759,6 +759,13 @@ int prepare(PlanBuild& b, int kind, const gna_model* model, const gna_problem* p
   p->shape = sh;
   compute_layout(p, b);
   rc = apply_shape(p, sh, nullptr);  // validates; no workspace yet, nothing uploaded
+  if (!rc && kind == kChain && !sh.mfma && !p->tail_pin && p->n_tiles > 1) {
+    // Several tiles per point: by default the point pass and the per-point
+    // tails go in two launches (the launch boundary orders the bin sums,
+    // instead of a release and a completion count in every tile).
+    sh.split = 1;
+    rc = apply_shape(p, sh, nullptr);
+  }
   if (rc) {
     delete_plan(b);
     return rc;

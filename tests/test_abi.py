@@ -121,7 +121,7 @@ def test_chain_validation_errors(lib):
     assert _sizes(lib, pr, opts={"threads": 100})[0] == -1
     assert _sizes(lib, pr, opts={"lanes_per_bin": 3})[0] == -1
     assert _sizes(lib, pr, opts={"split_tail": 3})[0] == -1
-    assert _sizes(lib, pr, opts={"split_tail": 2})[0] == -1  # chain plans have no split tail
+    assert _sizes(lib, pr, opts={"split_tail": 2})[0] == 0   # two-launch chain
     big = W.problem(W.uniform_edges(5000), 3, [52.5])
     big["data"] = np.ones(5000)
     assert _sizes(lib, big)[0] == -1

@@ -71,6 +71,8 @@ def test_cfg0_fp64_single_tile(cfg0, ti):
 def test_cfg0_fp64_multi_tile_shapes(cfg0, opts):
     P = np.atleast_2d(THETAS[1])
     plan = _plan(cfg0, smear_mfma=0, **opts)
+    # Automatic tail: two launches when a point has several tiles.
+    assert plan.shape()["split_tail"] == (plan.shape()["n_tiles"] > 1)
     ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True)
     for _ in range(3):  # counters and queue reset themselves between launches
         got = _eval(plan, P)
@@ -310,11 +312,13 @@ def test_wide_chain_vectors_in_scratch(wide, opts, prec):
     dict(threads=128, lanes_per_bin=2, chunks=3),   # hand-off; one chunk per slice
 ])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_chain_without_gradient(cfg0, opts, prec):
+@pytest.mark.parametrize("split_tail", [1, 2])
+def test_chain_without_gradient(cfg0, opts, prec, split_tail):
     """chi^2 and the prediction without the gradient (the tail carries mu0
-    alone), against the oracle and against the same plan's gradient launch."""
+    alone), against the oracle and against the same plan's gradient launch;
+    one launch with a hand-off (1) and point pass + tail launch (2)."""
     P = np.atleast_2d(THETAS[1])
-    plan = _plan(cfg0, prec=prec, smear_mfma=0, **opts)
+    plan = _plan(cfg0, prec=prec, smear_mfma=0, split_tail=split_tail, **opts)
     Pt = torch.tensor(P, dtype=torch.float64, device=DEV)
     out = plan.eval(Pt, grad=False, pred=True)
     torch.cuda.synchronize()
@@ -328,3 +332,39 @@ def test_chain_without_gradient(cfg0, opts, prec):
     assert np.array_equal(got["chi2"], with_grad["chi2"])
     assert np.array_equal(got["pred"], with_grad["pred"])
     assert plan.status() == 0
+
+
+@pytest.mark.parametrize("case,opts", [
+    ("cfg0", dict(threads=512, lanes_per_bin=1, chunks=1)),              # one tile per point
+    ("cfg0", dict(threads=64, lanes_per_bin=4, chunks=5)),               # 15 blocks x 5 chunks
+    ("cfg0", dict(threads=256, lanes_per_bin=8, chunks=2, persistent=1)),
+    ("cfg2", dict(threads=512, lanes_per_bin=64, chunks=8)),             # (point, baseline) items
+    ("cfg2", dict(threads=256, lanes_per_bin=32, chunks=16, persistent=1)),
+    ("wide", dict(threads=512, lanes_per_bin=2, chunks=3)),              # vectors in scratch
+])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_chain_split_tail_equals_fused_tail(request, case, opts, prec):
+    """Two-launch chain (every tile stores its bin sums, then one work-group
+    per point runs its tail) against the one-launch hand-off of the same
+    shape: the same sums in the same order, so the same bits; against the
+    oracle too; three points, two evaluations (nothing carries over)."""
+    pr = request.getfixturevalue(case)
+    if case == "wide":
+        pr = pr[0]
+    P = np.stack([THETAS[1], THETAS[0], THETAS[1] * np.array([0.99, 1.01, 0.97, 1.1, 0.98])])
+    split = _plan(pr, B=3, prec=prec, smear_mfma=0, split_tail=2, **opts)
+    fused = _plan(pr, B=3, prec=prec, smear_mfma=0, split_tail=1, **opts)
+    assert split.shape()["split_tail"] == 1 and fused.shape()["split_tail"] == 0
+    ref = oracle.chain(pr, MODEL, P, grad=True, nu=True, n_threads=8)
+    want = _eval(fused, P)
+    for _ in range(2):
+        got = _eval(split, P)
+        for k in ("chi2", "grad", "pred"):
+            assert np.array_equal(got[k], want[k]), k
+    if prec == "fp64":
+        _check_fp64(got, ref, P)
+    else:
+        assert np.max(rel_err(got["pred"], ref["nu"])) <= 1e-5
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= 1e-4
+    assert split.status() == 0 and fused.status() == 0
+

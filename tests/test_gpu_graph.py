@@ -58,13 +58,16 @@ def test_graph_single_point_chain():
     _check_replays(plan, np.array([W.THETA0]), np.array([W.THETA0 * 1.01]))
 
 
-def test_graph_multi_tile_chain():
-    """Several tiles per point hand off through counters that each launch resets."""
+@pytest.mark.parametrize("split_tail", [1, 2])
+def test_graph_multi_tile_chain(split_tail):
+    """Several tiles per point: handing off through counters that each launch
+    resets (1), or a point pass and a tail launch (2)."""
     import paper_1804_07682_amd as gna
     pr = with_data(W.problem(W.uniform_edges(240), 5, [52.5], n_sub=8), MODEL, W.SEED)
     plan = gna.Chain(pr, MODEL, max_batch=2, device=DEV,
-                     opts={"smear_mfma": 0, "threads": 256, "lanes_per_bin": 8, "chunks": 4})
-    assert plan.shape()["n_tiles"] > 1
+                     opts={"smear_mfma": 0, "threads": 256, "lanes_per_bin": 8, "chunks": 4,
+                           "split_tail": split_tail})
+    assert plan.shape()["n_tiles"] > 1 and plan.shape()["split_tail"] == split_tail - 1
     _check_replays(plan, W.config3_params(1, 2), W.config3_params(2, 1))
 
 

@@ -197,7 +197,9 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
   __syncthreads();
 
   const double norm = th[4];
-  const int wave = tid / kWave, lane = tid - (tid / kWave) * kWave;
+  // (wave is uniform over the wavefront: its descriptor reads are scalar.)
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int lane = tid - (tid / kWave) * kWave;
   const int nwaves = NT / kWave;
   const int ns = pd.n_slices;
   const SliceDev* slices = a.slices + pd.slice_off;
@@ -523,25 +525,17 @@ __global__ void __launch_bounds__(1024) chain_kernel(ChainArgs<R> a, int vs, int
   }
 }
 
-// ---- split tail (uneven batches) ------------------------------------------
-// With a split tail the point pass above only writes every fit's bin sums;
-// two more launches finish the chain with the whole GPU on each step:
-//   tail_fwd    one wavefront per 64-row slice of any fit: nu_i = norm (R mu0)_i,
-//               the chi^2 terms, gnu_i = 2 (1 - d_i / nu_i) and, with the
-//               gradient, the tangent rows (R J0)_ic, all from one pass over
-//               the slice's diagonals; the slice's partials are
-//               sum_i chi2 terms, sum_i gnu_i (R J0)_ic and sum_i gnu_i (R mu0)_i
-//   tail_final  per fit: the slice partials added in a fixed order
-// Carrying the four tangent columns through the smearing replaces the
-// adjoint pass over R^T: sum_j gmu_j J0_jc = sum_i gnu_i (R J0)_ic, so the
-// band is read once per evaluation instead of twice.
 // Two-launch form of a chain plan (split tail): after the point pass of all
 // tiles, one work-group per parameter point sums the point's chunks and runs
 // its tail.  The launch boundary orders the sums; there is no completion
 // counter and no cross-work-group release, which a one-launch hand-off pays
-// in every tile (an L2 write-back, then an atomic round trip).
+// in every tile (an L2 write-back, then an atomic round trip).  The tail has
+// its own width, kChainTailThreads lanes whatever the point pass used (its
+// diagonal chunks per slice follow the width, so the last bits match the
+// one-launch form of a shape of that width).
 template <class R, bool GRAD>
-__global__ void __launch_bounds__(1024) chain_tail_kernel(ChainArgs<R> a, int vs, int kf_cap) {
+__global__ void __launch_bounds__(kChainTailThreads) chain_tail_kernel(ChainArgs<R> a, int vs,
+                                                                      int kf_cap) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   TileLds L{lds_raw, (int)blockDim.x, vs, kf_cap};
   const int point = blockIdx.x;
@@ -557,6 +551,18 @@ __global__ void __launch_bounds__(1024) chain_tail_kernel(ChainArgs<R> a, int vs
   point_tail<R, GRAD>(a, a.probs[0], point, th, bad, L, false);
 }
 
+// ---- split tail (uneven batches) ------------------------------------------
+// With a split tail the point pass above only writes every fit's bin sums;
+// two more launches finish the chain with the whole GPU on each step:
+//   tail_fwd    one wavefront per 64-row slice of any fit: nu_i = norm (R mu0)_i,
+//               the chi^2 terms, gnu_i = 2 (1 - d_i / nu_i) and, with the
+//               gradient, the tangent rows (R J0)_ic, all from one pass over
+//               the slice's diagonals; the slice's partials are
+//               sum_i chi2 terms, sum_i gnu_i (R J0)_ic and sum_i gnu_i (R mu0)_i
+//   tail_final  per fit: the slice partials added in a fixed order
+// Carrying the four tangent columns through the smearing replaces the
+// adjoint pass over R^T: sum_j gmu_j J0_jc = sum_i gnu_i (R J0)_ic, so the
+// band is read once per evaluation instead of twice.
 template <class R>
 struct TailArgs {
   const ProbDev* probs;
@@ -909,13 +915,14 @@ int launch_t(gna_plan* p, const ChainArgs<R>& a, hipStream_t s) {
 
 template <class R>
 int launch_point_tails(gna_plan* p, const ChainArgs<R>& a, int32_t B, bool grad, hipStream_t s) {
-  const Shape& sh = p->shape;
-  const ChainLds cl = chain_lds(p, sh);  // the fused tail's LDS (vectors, partials, reductions)
+  Shape ts = p->shape;
+  ts.threads = kChainTailThreads;
+  const ChainLds cl = chain_lds(p, ts);  // the fused tail's layout at the tail's width
   if (grad)
-    hipLaunchKernelGGL((chain_tail_kernel<R, true>), dim3((unsigned)B), dim3(sh.threads), cl.bytes,
-                       s, a, cl.vs, cl.kf_cap);
+    hipLaunchKernelGGL((chain_tail_kernel<R, true>), dim3((unsigned)B), dim3(kChainTailThreads),
+                       cl.bytes, s, a, cl.vs, cl.kf_cap);
   else
-    hipLaunchKernelGGL((chain_tail_kernel<R, false>), dim3((unsigned)B), dim3(sh.threads),
+    hipLaunchKernelGGL((chain_tail_kernel<R, false>), dim3((unsigned)B), dim3(kChainTailThreads),
                        cl.bytes, s, a, cl.vs, cl.kf_cap);
   return check_hip(hipGetLastError(), "chain_tail_kernel launch");
 }

@@ -25,6 +25,8 @@ constexpr double kBandZ = 6.0;      // erf(z) == +-1 in FP64 beyond |z| = 5.93
 // of queue entries after its last tile (with the CU count and the
 // work-group size: about one turnover of the resident work-groups).
 constexpr int kQueuedLagWaves = 16;
+// Lanes of the per-point tail launch of a two-launch chain plan.
+constexpr int kChainTailThreads = 512;
 
 // ---- device-side descriptors (live in the workspace) -----------------------
 struct ProbDev {

@@ -55,6 +55,34 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// v of the lane that DPP control CTRL selects (0 where the row / bank masks
+// disable the lane or the source lane does not exist), both halves moved.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK,
+                                             BANK_MASK, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+
+// Sum of v over the wavefront's 64 lanes, complete in lane 63: a prefix sum
+// within each row of 16 lanes (shifts by 1, 2, 3, then 4 and 8 on the upper
+// banks), then row 0's total broadcast into rows 1 and 3 and lane 31's into
+// rows 2 and 3.  Data-parallel-primitive moves between lanes of a row take
+// a few cycles, against an LDS round trip for each step of a shuffle.
+__device__ __forceinline__ double wave_total(double v) {
+  double s = v + dpp_take<0x111, 0xf, 0xf>(v);  // row_shr:1
+  s += dpp_take<0x112, 0xf, 0xf>(v);            // row_shr:2
+  s += dpp_take<0x113, 0xf, 0xf>(v);            // row_shr:3
+  s += dpp_take<0x114, 0xf, 0xe>(s);            // row_shr:4, banks 1-3
+  s += dpp_take<0x118, 0xf, 0xc>(s);            // row_shr:8, banks 2-3
+  s += dpp_take<0x142, 0xa, 0xf>(s);            // row_bcast:15 into rows 1, 3
+  s += dpp_take<0x143, 0xc, 0xf>(s);            // row_bcast:31 into rows 2, 3
+  return s;
+}
+
 // Dynamic LDS of one work-group (sizes in chain_lds):
 //   vec   [5][vs]             mu0 and the four J0 columns of the point
 //                             (vs = 0: they stay in the scratch region)
@@ -147,6 +175,41 @@ __device__ __forceinline__ R sum_chunks(const R* sc, int C, int comp, int nb, in
   return s;
 }
 
+// vl[c vs + jj] = the chunk sum (as sum_chunks) of entry e = c nb + jj, for
+// this thread's entries e = tid, tid + NT, ... < n: U entries at a time, all
+// their chunk loads in flight together.
+template <class R, int U>
+__device__ __forceinline__ void chunk_sums_to_lds(const R* sc, int C, int nb, int n, R* vl, int vs,
+                                                  int tid, int NT) {
+  for (int e0 = tid; e0 < n; e0 += U * NT) {
+    R sum[U];
+    int cc[U], jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + u * NT, n - 1);
+      cc[u] = e / nb;
+      jj[u] = e - cc[u] * nb;
+      sum[u] = R(0);
+    }
+    for (int c = 0; c < C; c += 8) {
+      R v[U][8];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          v[u][k] = (e0 + u * NT < n && c + k < C)
+                        ? sc[(int64_t)((c + k) * 5 + cc[u]) * nb + jj[u]] : R(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum[u] += v[u][k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * NT < n) vl[cc[u] * vs + jj[u]] = sum[u];
+  }
+}
+
 // Baseline constants of the current tile's problem, staged once per tile so
 // the per-baseline loop reads LDS (a broadcast) instead of waiting on memory.
 struct BaseLds {
@@ -159,9 +222,9 @@ struct BaseLds {
 // already in LDS), nu = norm R mu0 with the four tangent columns through R,
 // the chi^2 terms, the gradient, in one work-group.  vl / sc: the point's
 // vectors in LDS (L.vs > 0) or in chunk 0 of its scratch region.
-template <class R, bool GRAD>
+template <class R, bool GRAD, int UNROLL = 2, class BadF>
 __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, const double* th,
-                           bool bad, const TileLds& L, bool single) {
+                           BadF bad_of, const TileLds& L, bool single) {
   const int tid = threadIdx.x;
   const int NT = blockDim.x;
   const int nb = pd.n_bins;
@@ -172,19 +235,23 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
   constexpr int NC = GRAD ? 5 : 1;
   const int C = pd.C;
   const double* dat = a.data + pd.bin_off;
+  // (wave is uniform over the wavefront: its descriptor reads are scalar.)
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int lane = tid - (tid / kWave) * kWave;
+  const int nwaves = NT / kWave;
+  const int ns = pd.n_slices;
+  const SliceDev* slices = a.slices + pd.slice_off;
+  // Smearing work items (slice, chunk of its diagonals) over all waves; the
+  // descriptor of this wavefront's first item is requested now.
+  const int Kf = min(L.kf_cap, max(1, nwaves / ns));
+  const SliceDev sd_first = slices[min(wave, ns * Kf - 1) / Kf];
   // This thread's first row of the chi^2 pass below when the slices are
   // split into chunks (row tid); requested now so that its latency overlaps.
   const double d_first = (tid < nb) ? dat[tid] : 0.0;
   // Entries e = c nb + jj of the NC vectors, two per trip so that two
   // entries' chunk loads are in flight together.
   if (vlds) {
-    if (!single) {
-#pragma unroll 2
-      for (int e = tid; e < NC * nb; e += NT) {
-        const int c = e / nb, jj = e - (e / nb) * nb;
-        vl[c * L.vs + jj] = sum_chunks<R>(sc, C, c, nb, jj);
-      }
-    }
+    if (!single) chunk_sums_to_lds<R, UNROLL>(sc, C, nb, NC * nb, vl, L.vs, tid, NT);
   } else if (C > 1) {
     // In place into chunk 0: each entry is read and written by one thread.
 #pragma unroll 2
@@ -197,12 +264,6 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
   __syncthreads();
 
   const double norm = th[4];
-  // (wave is uniform over the wavefront: its descriptor reads are scalar.)
-  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-  const int lane = tid - (tid / kWave) * kWave;
-  const int nwaves = NT / kWave;
-  const int ns = pd.n_slices;
-  const SliceDev* slices = a.slices + pd.slice_off;
   double* pred = a.pred ? (a.tiles ? a.pred + pd.bin_off : a.pred + (int64_t)point * nb)
                         : nullptr;
   double chi = 0.0;
@@ -223,14 +284,12 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
     if (pred) pred[i] = nu;
   };
 
-  // Smearing: work items (slice, chunk of its diagonals) over all waves.  With
-  // one chunk per slice each wavefront finishes its own rows.
-  const int Kf = min(L.kf_cap, max(1, nwaves / ns));
+  // Smearing: each wavefront's items; with one chunk per slice each
+  // wavefront finishes its own rows.
   const int PS = ns * kSlice;
   R* part = L.part<R>();  // [Kf][NC][PS]: Kf * PS <= threads
-  for (int item = wave; item < ns * Kf; item += nwaves) {
+  auto run_item = [&](int item, const SliceDev& sd) {
     const int s = item / Kf, kap = item - (item / Kf) * Kf;
-    const SliceDev sd = slices[s];
     const int csz = (sd.nd + Kf - 1) / Kf;
     const int d0 = min(sd.nd, kap * csz), d1 = min(sd.nd, d0 + csz);
     const int i = s * kSlice + lane;
@@ -248,7 +307,9 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
         for (int c = 0; c < NC; ++c) part[(kap * NC + c) * PS + i] = acc[c];
       }
     }
-  }
+  };
+  if (wave < ns * Kf) run_item(wave, sd_first);
+  for (int item = wave + nwaves; item < ns * Kf; item += nwaves) run_item(item, slices[item / Kf]);
   if (Kf > 1) {
     __syncthreads();
     for (int i = tid; i < nb; i += NT) {
@@ -265,12 +326,12 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
   double* red = L.red<R>();
-  chi = wave_sum(chi);
+  chi = wave_total(chi);
   if (GRAD) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
+    for (int c = 0; c < 5; ++c) gs[c] = wave_total(gs[c]);
   }
-  if (lane == 0) {
+  if (lane == kWave - 1) {
     red[wave * 6] = chi;
     if (GRAD) {
 #pragma unroll
@@ -287,6 +348,7 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
         for (int c = 0; c < 5; ++c) g5[c] += red[w * 6 + 1 + c];
       }
     }
+    const bool bad = bad_of();  // (after the sums: the parameters' loads are long done)
     if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
     a.chi2[point] = bad ? NAN : 2.0 * chisum;
@@ -490,7 +552,7 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     __syncthreads();
   }
 
-  point_tail<R, GRAD>(a, pd, td.point, th, k.bad, L, single);
+  point_tail<R, GRAD>(a, pd, td.point, th, [&] { return k.bad; }, L, single);
 }
 
 template <class R, bool GRAD, bool PERSIST, bool SPLIT>
@@ -547,8 +609,10 @@ __global__ void __launch_bounds__(kChainTailThreads) chain_tail_kernel(ChainArgs
 #pragma unroll
     for (int c = 0; c < 5; ++c) th[c] = a.pin[c];
   }
-  const bool bad = pee_coef<R>(th).bad;
-  point_tail<R, GRAD>(a, a.probs[0], point, th, bad, L, false);
+  // The chunk sums go out before anything waits for the parameters: P_ee's
+  // mixing check is taken at the end, norm when the first row finishes.
+  point_tail<R, GRAD, 4>(a, a.probs[0], point, th, [&] { return pee_coef<R>(th).bad; }, L,
+                         false);
 }
 
 // ---- split tail (uneven batches) ------------------------------------------

@@ -29,6 +29,7 @@
 
 #include "gna_internal.h"
 #include "gna_math.h"
+#include "lanes.h"
 
 namespace gna {
 namespace {
@@ -53,34 +54,6 @@ template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
-}
-
-// v of the lane that DPP control CTRL selects (0 where the row / bank masks
-// disable the lane or the source lane does not exist), both halves moved.
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ double dpp_take(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, BANK_MASK, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK,
-                                             BANK_MASK, true);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
-                                          (unsigned long long)(unsigned)lo));
-}
-
-// Sum of v over the wavefront's 64 lanes, complete in lane 63: a prefix sum
-// within each row of 16 lanes (shifts by 1, 2, 3, then 4 and 8 on the upper
-// banks), then row 0's total broadcast into rows 1 and 3 and lane 31's into
-// rows 2 and 3.  Data-parallel-primitive moves between lanes of a row take
-// a few cycles, against an LDS round trip for each step of a shuffle.
-__device__ __forceinline__ double wave_total(double v) {
-  double s = v + dpp_take<0x111, 0xf, 0xf>(v);  // row_shr:1
-  s += dpp_take<0x112, 0xf, 0xf>(v);            // row_shr:2
-  s += dpp_take<0x113, 0xf, 0xf>(v);            // row_shr:3
-  s += dpp_take<0x114, 0xf, 0xe>(s);            // row_shr:4, banks 1-3
-  s += dpp_take<0x118, 0xf, 0xc>(s);            // row_shr:8, banks 2-3
-  s += dpp_take<0x142, 0xa, 0xf>(s);            // row_bcast:15 into rows 1, 3
-  s += dpp_take<0x143, 0xc, 0xf>(s);            // row_bcast:31 into rows 2, 3
-  return s;
 }
 
 // Dynamic LDS of one work-group (sizes in chain_lds):
@@ -475,12 +448,16 @@ __device__ void process_tile(const ChainArgs<R>& a, int64_t t, const TileLds& L,
     }
   }
   // Sum the G lanes of each bin (groups are aligned inside a wavefront).
-  for (int off = G >> 1; off > 0; off >>= 1) {
-    mu += __shfl_xor(mu, off, kWave);
-    if (GRAD) {
+  if (GRAD) {
+    R v[5] = {mu, J[0], J[1], J[2], J[3]};
+    group_sums(v, G);
+    mu = v[0];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) J[c] += __shfl_xor(J[c], off, kWave);
-    }
+    for (int c = 0; c < 4; ++c) J[c] = v[1 + c];
+  } else {
+    R v[1] = {mu};
+    group_sums(v, G);
+    mu = v[0];
   }
 
   const int nb = pd.n_bins;

@@ -20,6 +20,7 @@
 
 #include "gna_internal.h"
 #include "gna_math.h"
+#include "lanes.h"
 
 namespace gna {
 namespace {
@@ -181,52 +182,6 @@ __host__ __device__ inline size_t scan_lds(int nL, int nq, int mt, int nwaves, i
          a16((size_t)nwaves * kScanN * 6 * 8) + (share ? a16((size_t)mt * 16 * kTab * 8) : 0) +
          (sizeof(R) == 4 ? a16((size_t)kLogTab * 16) : 0) +
          a16((size_t)rblocks * kBlk * sizeof(R));
-}
-
-// Cross-lane moves without the LDS crossbar (a shuffle is an LDS round trip
-// per 32-bit word).  Word of lane l ^ O, O = 16 or 32: the row swaps of
-// gfx950 exchange rows 1, 3 of one operand with rows 0, 2 of the other (O =
-// 16) or the upper half with the lower half (O = 32); with both operands the
-// same word, the first result holds the partner's word on lanes with bit O
-// set, the second on the others.
-template <int O>
-__device__ __forceinline__ unsigned xor_word_rows(unsigned w) {
-  const bool upper = (threadIdx.x & O) != 0;
-  if constexpr (O == 16) {
-    const auto r = __builtin_amdgcn_permlane16_swap(w, w, false, false);
-    return upper ? r[0] : r[1];
-  } else {
-    const auto r = __builtin_amdgcn_permlane32_swap(w, w, false, false);
-    return upper ? r[0] : r[1];
-  }
-}
-// Word of a partner lane within a row of 16, by DPP: O = 1, 2 are the
-// exchanges l ^ 1, l ^ 2 in each quad; O = 4, 8 are the mirrors within 8
-// and 16 lanes, which pair lane l with a lane of the other half, and so give
-// the same sum as l ^ O inside a butterfly taken in the order 1, 2, 4, 8
-// (after the lower steps every lane of a quad, an octet, holds the same
-// partial sum, bit for bit: IEEE addition commutes).
-template <int O>
-__device__ __forceinline__ unsigned xor_word_dpp(unsigned w) {
-  constexpr int ctrl = O == 1 ? 0xB1 : O == 2 ? 0x4E : O == 4 ? 0x141 : 0x140;
-  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)w, ctrl, 0xf, 0xf, false);
-}
-template <int O>
-__device__ __forceinline__ unsigned xor_word(unsigned w) {
-  if constexpr (O >= 16)
-    return xor_word_rows<O>(w);
-  else
-    return xor_word_dpp<O>(w);
-}
-template <int O>
-__device__ __forceinline__ double partner(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = xor_word<O>((unsigned)b), hi = xor_word<O>((unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-template <int O>
-__device__ __forceinline__ float partner(float v) {
-  return __uint_as_float(xor_word<O>(__float_as_uint(v)));
 }
 
 // v + (lane l ^ 16) + ..., summed as the butterfly over 16 and 32.
@@ -404,23 +359,7 @@ __global__ void __launch_bounds__(NT, WPE) scan_kernel(ScanArgs<R> a) {
             }
           }
         }
-        // Butterfly over the G lanes of a bin (G <= 16, steps 1, 2, 4, 8).
-        if (G > 1) {
-#pragma unroll
-          for (int c = 0; c < kTab; ++c) sum[c] += partner<1>(sum[c]);
-        }
-        if (G > 2) {
-#pragma unroll
-          for (int c = 0; c < kTab; ++c) sum[c] += partner<2>(sum[c]);
-        }
-        if (G > 4) {
-#pragma unroll
-          for (int c = 0; c < kTab; ++c) sum[c] += partner<4>(sum[c]);
-        }
-        if (G > 8) {
-#pragma unroll
-          for (int c = 0; c < kTab; ++c) sum[c] += partner<8>(sum[c]);
-        }
+        group_sums(sum, G);  // the G lanes of a bin (G <= 16)
         if (j < nb && sub == 0) {
           // Row j of the operand in 16-byte stores (fewer, wider LDS writes
           // than one per sum: the rows of neighbouring lanes share banks).

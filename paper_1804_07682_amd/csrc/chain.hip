@@ -50,12 +50,6 @@ __device__ __forceinline__ float rfma<float>(float a, float b, float c) {
 template <class R>
 constexpr int kTailBatch = sizeof(R) == 8 ? 8 : 16;
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
 // Dynamic LDS of one work-group (sizes in chain_lds):
 //   vec   [5][vs]             mu0 and the four J0 columns of the point
 //                             (vs = 0: they stay in the scratch region)
@@ -736,12 +730,12 @@ __device__ __forceinline__ void slice_tail(const A& a, int64_t item, int lane, R
   }
   if (badnu) __hip_atomic_fetch_or(a.status, (uint32_t)kBadPrediction, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-  chi = wave_sum(chi);
+  chi = wave_total(chi);
   if (GRAD) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) gs[c] = wave_sum(gs[c]);
+    for (int c = 0; c < 5; ++c) gs[c] = wave_total(gs[c]);
   }
-  if (lane == 0) {
+  if (lane == kWave - 1) {
     a.part[item * 6] = chi;
     if (GRAD) {
 #pragma unroll
@@ -762,7 +756,7 @@ __global__ void __launch_bounds__(kTailWaves * kWave) tail_fwd_kernel(TailArgs<R
 }
 
 // The chi^2 and gradient of fit f from its slice partials: lane s takes slice
-// s (a fit has at most kMaxBins / 64 = 64 of them), and the butterfly sums
+// s (a fit has at most kMaxBins / 64 = 64 of them), and the wavefront sums
 // are fixed-order.  Shared by the split and the queued tail.
 template <class R, bool GRAD, class A>
 __device__ __forceinline__ void fit_final(const A& a, int f, int lane) {
@@ -776,8 +770,8 @@ __device__ __forceinline__ void fit_final(const A& a, int f, int lane) {
     for (int c = 0; c < (GRAD ? 6 : 1); ++c) v[c] = q[c];
   }
 #pragma unroll
-  for (int c = 0; c < (GRAD ? 6 : 1); ++c) v[c] = wave_sum(v[c]);
-  if (lane != 0) return;
+  for (int c = 0; c < (GRAD ? 6 : 1); ++c) v[c] = wave_total(v[c]);
+  if (lane != kWave - 1) return;
   const bool bad = pee_coef<R>(th).bad;
   if (bad) __hip_atomic_fetch_or(a.status, (uint32_t)kBadMixing, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);

@@ -233,3 +233,29 @@ def test_item_nodes_validate():
         g.pee_items(t, a, b)                    # sin 2phi items where sin^2 is needed
     with pytest.raises(gna.GnaError):
         g.osc_item(pts, 52.5, a, b, 3)
+
+
+def test_chain_node_multi_tile_point():
+    """A chain node whose one point spans many tiles (8 baselines, 420
+    quadrature points per bin): the plan runs the point pass and the per-point
+    tail as two launches, with the node's parameters passed by value to both;
+    against the oracle, for two parameter points in a row."""
+    import paper_1804_07682_amd as gna
+    pr = with_data(W.config2(), MODEL, W.SEED + 2)
+    g = gna.Graph(DEV)
+    v = {nm: g.variable(nm, W.THETA0[i]) for i, nm in enumerate(NAMES)}
+    pts = g.points(pr, MODEL)
+    c64 = g.chain(pts, [v[k] for k in NAMES], "fp64")
+    cmx = g.chain(pts, [v[k] for k in NAMES], "mixed")
+    g.bind()
+    for theta in (W.THETA0 * np.array([1.01, 0.99, 1.02, 0.97, 1.0]),
+                  W.THETA0 * np.array([0.98, 1.02, 1.0, 1.03, 1.01])):
+        for i, nm in enumerate(NAMES):
+            g.set(v[nm], theta[i])
+        ref = oracle.chain(pr, MODEL, theta, grad=True)
+        out = g.read(c64)
+        assert rel_err(out[0], ref["chi2"][0]) <= FP64_RTOL
+        assert np.max(grad_error(out[1:], ref["grad"][0], theta, ref["chi2"])) <= FP64_RTOL
+        mx = g.read(cmx)
+        assert rel_err(mx[0], ref["chi2"][0]) <= MIXED_CHI2_RTOL
+        assert np.max(grad_error(mx[1:], ref["grad"][0], theta, ref["chi2"])) <= MIXED_GRAD_TOL

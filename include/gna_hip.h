@@ -531,7 +531,9 @@ int gna_graph_chi2(gna_graph* graph, int32_t nu, int32_t points, int32_t* node_o
 int gna_graph_workspace_size(const gna_graph* graph, size_t* bytes);
 /* Place outputs in workspace_dev (256-byte aligned, >= the size above) and
  * compute the configuration tables on `stream`.  Synchronous.  The graph
- * keeps the workspace until it is destroyed. */
+ * keeps the workspace until it is destroyed.  The host mirrors of all
+ * outputs go in one page-locked host allocation made here (host memory, one
+ * double per output element; freed by gna_graph_destroy). */
 int gna_graph_bind(gna_graph* graph, void* workspace_dev, size_t workspace_bytes, void* stream);
 /* Change a variable: taints its dependents (no computation). */
 int gna_graph_set(gna_graph* graph, int32_t var, double value);

@@ -69,7 +69,7 @@ struct Node {
   const double* table = nullptr;  // configuration tables: output lives in a plan
   bool dirty = true;
   int target = GNA_TARGET_GPU;
-  std::vector<double> host;  // host mirror of the output
+  double* host = nullptr;    // host mirror of the output (pinned, placed at bind)
   bool host_valid = false, dev_valid = false;
   int64_t evals = 0, d2h = 0, h2d = 0;
   int64_t failovers = 0;     // GPU failures this node recovered from on the CPU
@@ -257,6 +257,7 @@ struct gna_graph {
   std::vector<std::vector<int>> consumers;  // nodes reading each node
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
+  double* pinned = nullptr;  // every node's host mirror, in page-locked host memory
   bool bound = false;
   bool failover = false;  // recompute a node on the CPU when its GPU form fails
 };
@@ -313,8 +314,7 @@ int ensure_host(gna_graph* g, int id, hipStream_t s) {
   Node& nd = g->nodes[id];
   if (nd.host_valid) return GNA_OK;
   if (!nd.dev_valid) return fail(GNA_E_INVAL, "graph node %d has no valid copy", id);
-  nd.host.resize((size_t)nd.n);
-  int rc = check_hip(hipMemcpyAsync(nd.host.data(), dev_ptr(g, nd), (size_t)nd.n * 8,
+  int rc = check_hip(hipMemcpyAsync(nd.host, dev_ptr(g, nd), (size_t)nd.n * 8,
                                     hipMemcpyDeviceToHost, s),
                      "hipMemcpyAsync (graph node to host)");
   if (rc || (rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize (graph node to host)")))
@@ -330,7 +330,7 @@ int ensure_dev(gna_graph* g, int id, hipStream_t s) {
   Node& nd = g->nodes[id];
   if (nd.dev_valid) return GNA_OK;
   if (!nd.host_valid) return fail(GNA_E_INVAL, "graph node %d has no valid copy", id);
-  int rc = check_hip(hipMemcpyAsync(dev_ptr(g, nd), nd.host.data(), (size_t)nd.n * 8,
+  int rc = check_hip(hipMemcpyAsync(dev_ptr(g, nd), nd.host, (size_t)nd.n * 8,
                                     hipMemcpyHostToDevice, s),
                      "hipMemcpyAsync (graph node to device)");
   if (rc || (rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize (graph node to device)")))
@@ -380,9 +380,8 @@ int compute_cpu(gna_graph* g, int id, hipStream_t s) {
   int rc;
   for (int in : nd.inputs)
     if ((rc = ensure_host(g, in, s))) return rc;
-  nd.host.resize((size_t)nd.n);
-  double* out = nd.host.data();
-  auto in_h = [&](int k) { return g->nodes[nd.inputs[k]].host.data(); };
+  double* out = nd.host;
+  auto in_h = [&](int k) { return (const double*)g->nodes[nd.inputs[k]].host; };
   switch (nd.kind) {
     case kOscProb: {
       const double th[4] = {var(g, nd, 0), var(g, nd, 1), var(g, nd, 2), var(g, nd, 3)};
@@ -656,6 +655,7 @@ extern "C" int gna_graph_destroy(gna_graph* graph) {
     gna_plan_destroy(ge.plan);
     gna_plan_destroy(ge.plan_mixed);
   }
+  if (graph->pinned) (void)hipHostFree(graph->pinned);
   delete graph;
   return GNA_OK;
 }
@@ -1022,9 +1022,26 @@ extern "C" int gna_graph_bind(gna_graph* graph, void* workspace_dev, size_t work
     return fail(GNA_E_WORKSPACE, "gna_graph_bind: workspace %zu bytes, needs %zu",
                 workspace_bytes, need);
   hipStream_t s = (hipStream_t)stream;
+  // Host mirrors in page-locked memory (configuration stage): a read's
+  // device-to-host copy then goes straight to its destination, without the
+  // staging a pageable destination needs.
+  size_t mirror = 0;
+  for (const auto& nd : graph->nodes) mirror += (size_t)nd.n;
+  int rc;
+  if (!graph->pinned &&
+      (rc = check_hip(hipHostMalloc((void**)&graph->pinned, std::max<size_t>(mirror, 1) * 8,
+                                    hipHostMallocDefault),
+                      "hipHostMalloc (graph host mirrors)")))
+    return rc;
+  {
+    size_t o = 0;
+    for (auto& nd : graph->nodes) {
+      nd.host = graph->pinned + o;
+      o += (size_t)nd.n;
+    }
+  }
   graph->ws = (unsigned char*)workspace_dev;
   graph->ws_bytes = workspace_bytes;
-  int rc;
   for (auto& ge : graph->geoms) {
     // The configuration tables (E_k, f_k, the band of R, data) of a one-point
     // FP64 chain plan; the dense R the smearing node reads is expanded from it.
@@ -1113,7 +1130,7 @@ extern "C" int gna_graph_read(gna_graph* graph, int32_t node, double* host_out, 
                 (long long)graph->nodes[node].n);
   hipStream_t s = (hipStream_t)stream;
   if ((rc = evaluate(graph, node, s)) || (rc = ensure_host(graph, node, s))) return rc;
-  std::memcpy(host_out, graph->nodes[node].host.data(), (size_t)n * 8);
+  std::memcpy(host_out, graph->nodes[node].host, (size_t)n * 8);
   return GNA_OK;
 }
 

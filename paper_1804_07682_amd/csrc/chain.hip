@@ -215,8 +215,8 @@ __device__ void point_tail(const ChainArgs<R>& a, const ProbDev& pd, int point, 
   // This thread's first row of the chi^2 pass below when the slices are
   // split into chunks (row tid); requested now so that its latency overlaps.
   const double d_first = (tid < nb) ? dat[tid] : 0.0;
-  // Entries e = c nb + jj of the NC vectors, two per trip so that two
-  // entries' chunk loads are in flight together.
+  // Entries e = c nb + jj of the NC vectors, UNROLL per trip so that their
+  // chunk loads are in flight together (the in-place form: two).
   if (vlds) {
     if (!single) chunk_sums_to_lds<R, UNROLL>(sc, C, nb, NC * nb, vl, L.vs, tid, NT);
   } else if (C > 1) {

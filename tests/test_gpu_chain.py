@@ -185,9 +185,16 @@ def test_gl_nodes_match_oracle():
         assert np.max(np.abs(w - wo) / wo) <= 64 * 2.3e-16
 
 
-def test_domain_errors_latch(cfg0):
+@pytest.mark.parametrize("opts", [
+    {},                                                          # one tile per point
+    dict(threads=64, lanes_per_bin=4, chunks=5),                 # point pass + tail launch
+    dict(threads=64, lanes_per_bin=4, chunks=5, split_tail=1),   # one launch, hand-off
+], ids=["one_tile", "two_launch", "hand_off"])
+def test_domain_errors_latch(cfg0, opts):
+    """Invalid mixing (s12 > 1) and a zero prediction give NaN for that point
+    only and latch the status word, in each form of the tail."""
     import paper_1804_07682_amd as gna
-    plan = _plan(cfg0, B=2, smear_mfma=0)
+    plan = _plan(cfg0, B=2, smear_mfma=0, **opts)
     P = np.vstack([W.THETA0, W.THETA0])
     P[1, 2] = 1.5
     got = _eval(plan, P)

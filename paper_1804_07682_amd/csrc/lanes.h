@@ -103,7 +103,8 @@ __device__ __forceinline__ double dpp_take(double v) {
 // Sum of v over the wavefront's 64 lanes, complete in lane 63: a prefix sum
 // within each row of 16 lanes (shifts by 1, 2, 3, then 4 and 8 on the upper
 // banks), then row 0's total broadcast into rows 1 and 3 and lane 31's into
-// rows 2 and 3.
+// rows 2 and 3.  Called with every lane of the wavefront active (lanes with
+// nothing to add pass 0).
 __device__ __forceinline__ double wave_total(double v) {
   double s = v + dpp_take<0x111, 0xf, 0xf>(v);  // row_shr:1
   s += dpp_take<0x112, 0xf, 0xf>(v);            // row_shr:2

@@ -25,13 +25,21 @@ __device__ __forceinline__ float ffma(float a, float b, float c) { return __buil
 // parity of m is bit 0 of t (valid for |phi| < 2^50).  Two-part Cody-Waite
 // subtraction with FMAs: each step rounds an exactly formed product once; the
 // dropped third part of pi/2 contributes |m| * 1.5e-33, far below an ulp of r.
-__device__ __forceinline__ double reduce_pio2(double phi, bool& odd) {
+// tlo: the low word of t (bit 0 = parity of m).
+__device__ __forceinline__ double reduce_pio2_t(double phi, int& tlo) {
   const double magic = 6755399441055744.0;  // 1.5 * 2^52
   const double t = dfma(phi, GNA_TWO_OVER_PI, magic);
   const double m = t - magic;
-  odd = (__double2loint(t) & 1) != 0;
+  tlo = __double2loint(t);
   double r = dfma(-m, GNA_PIO2_1, phi);
   r = dfma(-m, GNA_PIO2_2, r);
+  return r;
+}
+
+__device__ __forceinline__ double reduce_pio2(double phi, bool& odd) {
+  int tlo;
+  const double r = reduce_pio2_t(phi, tlo);
+  odd = (tlo & 1) != 0;
   return r;
 }
 

@@ -39,12 +39,19 @@ struct PeeArgs {
   R w[kMaxBaselines];
 };
 
-// cos^2 phi in FP64 with the short sin^2 kernel (see pee_eval).
+// cos^2 phi in FP64 with the short sin^2 kernel (see pee_eval), without a
+// select: with h = 1/2 - sin^2 r, cos^2 phi = 1/2 + h for even m and
+// 1/2 - h (= sin^2 r) for odd m, so the parity (bit 0 of the reduction's t)
+// goes into the sign bit of h by one exclusive or.  Each form is within an
+// ulp and a half of the selected one (1/2 - sin^2 r is exact for sin^2 r >=
+// 1/4, and otherwise rounds at most 2^-54 absolute).
 __device__ __forceinline__ double cos2_phase_short(double phi) {
-  bool odd;
-  const double r = reduce_pio2(phi, odd);
-  const double s2 = sin2_kernel_short(r);
-  return odd ? s2 : 1.0 - s2;
+  int tlo;
+  const double r = reduce_pio2_t(phi, tlo);
+  const double h = 0.5 - sin2_kernel_short(r);
+  const unsigned long long hb = (unsigned long long)__double_as_longlong(h) ^
+                                ((unsigned long long)(unsigned)tlo << 63);
+  return __longlong_as_double((long long)hb) + 0.5;
 }
 
 template <class R>

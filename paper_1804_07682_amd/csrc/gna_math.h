@@ -241,17 +241,38 @@ struct PhaseTerms {
 
 template <class R>
 __device__ __forceinline__ PhaseTerms<R> phase_terms(double phi) {
-  bool odd;
-  const double r = reduce_pio2(phi, odd);
-  R s, c;
-  sincos_kernel(to_r<R>(r), s, c);
-  const R s2 = s * s, c2 = c * c;
-  const R sc = s * c;
-  PhaseTerms<R> out;
-  out.S = odd ? c2 : s2;                 // sin^2(m pi/2 + r)
-  out.C = odd ? s2 : c2;                 // cos^2(m pi/2 + r)
-  out.T = odd ? R(-2) * sc : R(2) * sc;  // sin(m pi + 2 r) = (-1)^m sin 2r
-  return out;
+  if constexpr (sizeof(R) == 8) {
+    // FP64 without selects: with h = 1/2 - sin^2 r and sigma = (-1)^m,
+    // sin^2 phi = 1/2 - sigma h, cos^2 phi = 1/2 + sigma h and
+    // sin 2phi = sigma sin 2r; sigma enters as the sign bit (bit 0 of the
+    // reduction's t, shifted to bit 63).  C - S = 2 sigma h exactly; S and
+    // C are within 2^-54 absolute of their correctly rounded values.
+    int tlo;
+    const double r = reduce_pio2_t(phi, tlo);
+    double s, c;
+    sincos_kernel(r, s, c);
+    const unsigned long long sg = (unsigned long long)(unsigned)tlo << 63;
+    const double h = __longlong_as_double(
+        (long long)((unsigned long long)__double_as_longlong(0.5 - s * s) ^ sg));
+    const double t = 2.0 * (s * c);
+    PhaseTerms<R> out;
+    out.S = 0.5 - h;
+    out.C = 0.5 + h;
+    out.T = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(t) ^ sg));
+    return out;
+  } else {
+    bool odd;
+    const double r = reduce_pio2(phi, odd);
+    R s, c;
+    sincos_kernel(to_r<R>(r), s, c);
+    const R s2 = s * s, c2 = c * c;
+    const R sc = s * c;
+    PhaseTerms<R> out;
+    out.S = odd ? c2 : s2;                 // sin^2(m pi/2 + r)
+    out.C = odd ? s2 : c2;                 // cos^2(m pi/2 + r)
+    out.T = odd ? R(-2) * sc : R(2) * sc;  // sin(m pi + 2 r) = (-1)^m sin 2r
+    return out;
+  }
 }
 
 // Terms of phi32 = phi31 - phi21 from those of phi21 and phi31 by the

@@ -382,3 +382,29 @@ def test_chain_split_tail_equals_fused_tail(request, case, opts, prec):
         assert np.max(rel_err(got["chi2"], ref["chi2"])) <= 1e-4
     assert split.status() == 0 and fused.status() == 0
 
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_chain_split_tail_batch_of_points(cfg0, prec):
+    """17 points through the two-launch chain at a many-tile shape (75 tiles
+    per point, one tail work-group per point): each point against the oracle
+    and, bit for bit, against the same point evaluated alone (per-point
+    scratch regions and tails do not interact)."""
+    P = W.config3_params(17, 1)
+    opts = dict(threads=64, lanes_per_bin=4, chunks=5, split_tail=2)
+    plan = _plan(cfg0, B=17, prec=prec, smear_mfma=0, **opts)
+    assert plan.shape()["split_tail"] == 1 and plan.shape()["n_tiles"] > 1
+    got = _eval(plan, P)
+    ref = oracle.chain(cfg0, MODEL, P, grad=True, nu=True, n_threads=8)
+    if prec == "fp64":
+        _check_fp64(got, ref, P)
+    else:
+        assert np.max(rel_err(got["pred"], ref["nu"])) <= MIXED_PRED_RTOL
+        assert np.max(rel_err(got["chi2"], ref["chi2"])) <= MIXED_CHI2_RTOL
+        assert np.max(grad_error(got["grad"], ref["grad"], P, ref["chi2"])) <= MIXED_GRAD_TOL
+    one = _plan(cfg0, B=1, prec=prec, smear_mfma=0, **opts)
+    for b in (0, 8, 16):
+        g1 = _eval(one, P[b])
+        for k in ("chi2", "grad", "pred"):
+            assert np.array_equal(g1[k][0], got[k][b]), (b, k)
+    assert plan.status() == 0

@@ -407,4 +407,7 @@ def test_chain_split_tail_batch_of_points(cfg0, prec):
         g1 = _eval(one, P[b])
         for k in ("chi2", "grad", "pred"):
             assert np.array_equal(g1[k][0], got[k][b]), (b, k)
+    part = _eval(plan, P[:5])  # fewer points than the plan was made for
+    for k in ("chi2", "grad", "pred"):
+        assert np.array_equal(part[k], got[k][:5]), k
     assert plan.status() == 0

@@ -260,9 +260,10 @@ typedef struct gna_problem {
  *                  (smearing, chi^2, gradient) runs in the work-group that
  *                  finishes its last tile; 2: the point pass only stores bin
  *                  sums and the tails run in later launches: for a chain
- *                  plan one work-group per parameter point (the same sums in
- *                  the same order as 1, bit for bit; the default when a
- *                  point has several tiles), for a fitset two launches with
+ *                  plan one 512-lane work-group per parameter point (the
+ *                  same sums as 1, in the same order, so the same bits, when
+ *                  the shape also has 512 lanes; the default when a point
+ *                  has several tiles), for a fitset two launches with
  *                  one wavefront per 64-row slice, then each fit's partials
  *                  added in a fixed order (the fitset default); 3 (fitset
  *                  plans only): queued tail, one launch: the persistent
